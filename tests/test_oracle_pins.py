@@ -1,0 +1,298 @@
+"""Pins of the FP64 CPU oracle against closed forms, brute force and invariants.
+
+Each pin is chosen so that a plausible slip in the oracle (a swapped projector,
+a wrong leg in the composite, a wrong rotation, a dropped scale) fails it.
+"""
+import numpy as np
+import pytest
+
+from oracle import brute, closed_forms as CF, ctmrg as O, gates
+from paper_1906_02220_amd import synth
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_onsager_two_quadratures_agree():
+    for beta in (0.2, 0.4, 0.6):
+        assert abs(CF.onsager_minus_beta_f(beta) - CF.onsager_minus_beta_f_single(beta)) < 1e-13
+
+
+def test_onsager_limits():
+    # beta -> 0: ln 2; large beta: 2 beta (two bonds per site, all aligned)
+    assert abs(CF.onsager_minus_beta_f(1e-8) - np.log(2.0)) < 1e-12
+    assert abs(CF.onsager_minus_beta_f(3.0) - 6.0) < 1e-8
+
+
+def test_onsager_correlation_is_derivative():
+    beta, h = 0.4, 1e-5
+    fd = (CF.onsager_minus_beta_f(beta + h) - CF.onsager_minus_beta_f(beta - h)) / (2 * h)
+    assert abs(CF.onsager_nn_correlation(beta) - 0.5 * fd) < 1e-9
+
+
+def test_houtappel_limits_and_series():
+    # K = 0: ln 2 per site
+    assert abs(CF.honeycomb_minus_beta_f(0.0, 0.0, 0.0) - np.log(2.0)) < 1e-14
+    # only z bonds: independent dimers, per site ln 2 + (1/2) ln cosh Kz
+    Kz = 0.7
+    assert abs(CF.honeycomb_minus_beta_f(0.0, 0.0, Kz) - (np.log(2.0) + 0.5 * np.log(np.cosh(Kz)))) < 1e-13
+    # weak anisotropic couplings: loop expansion through order t^10, error O(t^12)
+    K = (0.10, 0.15, 0.20)
+    t = np.tanh(K)
+    h2 = np.prod(t) ** 4
+    assert abs(CF.honeycomb_minus_beta_f(*K) - CF.honeycomb_high_temperature(*K)) < 2.0 * h2
+    K = (0.05, 0.075, 0.10)
+    assert abs(CF.honeycomb_minus_beta_f(*K) - CF.honeycomb_high_temperature(*K)) < 1e-13
+    # isotropic critical point: cosh 2K_c = 2 makes the integrand singular at theta = 0
+    Kc = 0.5 * np.arccosh(2.0)
+    c, s = np.cosh(2 * Kc), np.sinh(2 * Kc)
+    assert abs(c ** 3 + 1.0 - 3.0 * s * s) < 1e-12
+
+
+def test_houtappel_correlation_is_derivative():
+    K, h = [0.3, 0.5, 0.7], 1e-5
+    for w in range(3):
+        Kp, Km = list(K), list(K)
+        Kp[w] += h
+        Km[w] -= h
+        fd = 2.0 * (CF.honeycomb_minus_beta_f(*Kp) - CF.honeycomb_minus_beta_f(*Km)) / (2 * h)
+        assert abs(CF.honeycomb_bond_correlation(*K, which=w) - fd) < 1e-8
+
+
+# ---------------------------------------------------------------- Onsager pin
+
+def test_onsager_free_energy_converges_in_chi():
+    """Square Ising at beta = 0.4, chi = 4, 8, 16: ln kappa -> -beta f with a
+    monotonically shrinking error, below 1e-11 at chi = 16 (delta < 1e-10)."""
+    beta = 0.4
+    a = synth.ising_square_tensor(beta)
+    b = O.boundary_vector_classical(2)
+    exact = CF.onsager_minus_beta_f(beta)
+    errs = []
+    for chi in (4, 8, 16):
+        env, deltas = O.ctmrg(a, chi, b, 200, tol=1e-10)
+        assert deltas[-1] < 1e-10
+        errs.append(abs(np.log(O.kappa(env, a)) - exact))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-11
+
+
+def test_onsager_nearest_neighbour_correlation_from_ring():
+    """<s_i s_j> from the ring E with a dW/dbeta insertion on the l and r legs."""
+    beta, chi = 0.4, 16
+    a = synth.ising_square_tensor(beta)
+    env, _ = O.ctmrg(a, chi, O.boundary_vector_classical(2), 200, tol=1e-10)
+    E = O.ring(env)
+    za = np.sum(E * a)
+    ss = (np.sum(E * synth.ising_square_tensor_leg_derivative(beta, 1))
+          + np.sum(E * synth.ising_square_tensor_leg_derivative(beta, 3))) / za
+    assert abs(ss - CF.onsager_nn_correlation(beta)) < 1e-10
+    # the vertical bond gives the same value (u and d legs)
+    sv = (np.sum(E * synth.ising_square_tensor_leg_derivative(beta, 0))
+          + np.sum(E * synth.ising_square_tensor_leg_derivative(beta, 2))) / za
+    assert abs(sv - ss) < 1e-11
+
+
+# ---------------------------------------------------------------- honeycomb Ising pin
+
+@pytest.mark.parametrize("gamma", [0, 1, 2])
+def test_honeycomb_ising_through_composite(gamma):
+    """Anisotropic honeycomb Ising as a D = 2 two-sublattice state.  Fusing the
+    gamma bond into the composite must give ln kappa = 2 (-beta f) (two sites
+    per composite) and <sz_A sz_B> on the fused bond = d(2(-beta f))/dK_gamma.
+    Anisotropy makes a wrong leg assignment in the composite visible."""
+    K = (0.3, 0.5, 0.7)
+    A, B = synth.honeycomb_ising_tensors(*K)
+    env, a, Kc, D, deltas = O.environment_from_purification(A, B, gamma, 32, 200, tol=1e-11)
+    assert deltas[-1] < 1e-11
+    assert abs(np.log(O.kappa(env, a)) - 2.0 * CF.honeycomb_minus_beta_f(*K)) < 1e-10
+    zz = np.kron(synth.SZ, synth.SZ) * 4.0  # sigma^z sigma^z
+    aO = O.double_layer(Kc, O.full_operator(zz, 4))
+    assert abs(O.expect(env, a, aO) - CF.honeycomb_bond_correlation(*K, which=gamma)) < 1e-10
+
+
+def test_honeycomb_ising_isotropic_padded_and_gauged():
+    """Zero-pad D = 2 -> 4 and insert random G, G^-1 on every bond: the same
+    closed-form values at the dense D = 4 shape (exercises the cutoff path)."""
+    K = 0.4
+    A, B = synth.honeycomb_ising_tensors(K, K, K)
+    A, B = synth.pad_and_gauge(A, B, 4, seed=99)
+    env, a, Kc, D, _ = O.environment_from_purification(A, B, 2, 16, 60, tol=1e-11)
+    assert D == 4
+    assert abs(np.log(O.kappa(env, a)) - 2.0 * CF.honeycomb_minus_beta_f(K, K, K)) < 1e-9
+    zz = np.kron(synth.SZ, synth.SZ) * 4.0
+    aO = O.double_layer(Kc, O.full_operator(zz, 4))
+    assert abs(O.expect(env, a, aO) - CF.honeycomb_bond_correlation(K, K, K, which=2)) < 1e-9
+
+
+# ---------------------------------------------------------------- beta = 0 and one gate
+
+def test_singlet_product_state():
+    A, B = synth.singlet_tensors()
+    env, a, Kc, D, _ = O.environment_from_purification(A, B, 2, 4, 3)
+    assert abs(O.kappa(env, a) - 1.0) < 1e-14
+    rng = np.random.default_rng(3)
+    oA = synth.random_symmetric(2, 4)
+    oB = synth.random_symmetric(2, 5)
+    op = np.kron(oA, oB)
+    aO = O.double_layer(Kc, O.full_operator(op, 4))
+    assert abs(O.expect(env, a, aO) - np.trace(oA) * np.trace(oB) / 4.0) < 1e-14
+    del rng
+
+
+def test_singlet_padded_and_gauged_dense():
+    A, B = synth.singlet_tensors()
+    A, B = synth.pad_and_gauge(A, B, 3, seed=7)
+    env, a, Kc, D, _ = O.environment_from_purification(A, B, 2, 12, 6)
+    assert abs(O.kappa(env, a) - 1.0) < 1e-10
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    aO = O.double_layer(Kc, O.full_operator(H, 4))
+    assert abs(O.expect(env, a, aO) - np.trace(H) / 4.0) < 1e-10
+
+
+@pytest.mark.parametrize("gamma", [0, 2])
+def test_single_gate_layer_dimers(gamma):
+    """One gate exp(-tau H/2) on every gamma bond of the singlet state, split
+    at rank 4 (Fig. 3(b)): a product of dimers with kappa = Tr e^{-tau H}/4 and
+    <O> = Tr(O e^{-tau H}) / Tr e^{-tau H}."""
+    tau = 0.7
+    H = synth.random_symmetric(4, 11)
+    A, B = synth.singlet_tensors()
+    A, B = gates.apply_gate(A, B, gates.gate(H, tau), gamma)
+    assert A.shape[2 + gamma] == 4
+    A, B = synth.gauge_bonds(A, B, seed=3)
+    env, a, Kc, D, _ = O.environment_from_purification(A, B, gamma, 4, 4)
+    op = synth.kitaev_heisenberg_bond(0.3, 1)
+    norm, ex = CF.dimer_norm_and_expectation(H, tau, op)
+    assert abs(O.kappa(env, a) / norm - 1.0) < 1e-12
+    aO = O.double_layer(Kc, O.full_operator(op, 4))
+    assert abs(O.expect(env, a, aO) - ex) < 1e-12
+
+
+# ---------------------------------------------------------------- brute force
+
+def _min_kept_ratio(a, b, chi, sweeps):
+    arot = [O.rotate(a, k) for k in range(4)]
+    env = O.init_env(a.shape[0], chi, b)
+    worst = 1.0
+    for _ in range(sweeps):
+        for k in O.MOVE_ORDER:
+            s = O.left_move(env, arot, k, chi)
+            kept = s[s > O.EPS_CUT_DEFAULT * s[0]]
+            worst = min(worst, kept[-1] / s[0])
+    return env, worst
+
+
+@pytest.mark.parametrize("d,seed,bvec,chi,sweeps", [
+    (2, 12, (0.6, 0.8), 16, 1),
+    (2, 12, (0.6, 0.8), 16, 2),
+    (2, 12, (0.6, 0.8), 16, 3),
+    (3, 22, (0.6, 0.8, 0.3), 27, 1),
+    (3, 22, (0.6, 0.8, 0.3), 27, 2),
+])
+def test_untruncated_sweeps_equal_finite_lattice(d, seed, bvec, chi, sweeps):
+    """k sweeps from C = [[1]], T = b with nothing truncated represent the
+    (2k+1) x (2k+1) open lattice with boundary vector b: log Z (with every
+    divided-out scale added back) equals a row-transfer-matrix contraction.
+    The pin only holds while every singular value of the cut matrix is above
+    the cutoff; the case list keeps to such inputs and the test checks it."""
+    a = synth.random_site_tensor(d, seed)
+    if d == 3:
+        a = a + np.einsum('ud,lr->uldr', np.eye(d), np.eye(d)) / 0.3
+        a /= np.abs(a).max()
+    b = np.array(bvec)
+    env, worst = _min_kept_ratio(a, b, chi, sweeps)
+    assert worst > 1e-11
+    lz, sg = O.log_z(env, a)
+    L = 2 * sweeps + 1
+    lzb, sgb = brute.finite_lattice_log_z(a, b, L, L)
+    assert sg == sgb
+    assert abs(lz - lzb) < 1e-10 * max(1.0, abs(lzb))
+
+
+def test_untruncated_double_layer_one_sweep():
+    A, B = synth.random_purification(2, 7)
+    a = O.double_layer(O.composite(A, B, 2))
+    b = O.boundary_vector_double_layer(2)
+    env, worst = _min_kept_ratio(a, b, 16, 1)
+    assert worst > 1e-11
+    lz, _ = O.log_z(env, a)
+    lzb, _ = brute.finite_lattice_log_z(a, b, 3, 3)
+    assert abs(lz - lzb) < 1e-11 * abs(lzb)
+
+
+def test_brute_force_matches_direct_sum_on_tiny_lattice():
+    """The transfer-matrix contraction itself against an explicit sum over all
+    bond configurations of a 2 x 2 lattice."""
+    a = synth.random_site_tensor(2, 4)
+    b = np.array([0.3, -1.1])
+    lz, sg = brute.finite_lattice_log_z(a, b, 2, 2)
+    # 2x2 sites: internal bonds h0 (row 0), h1 (row 1), v0 (col 0), v1 (col 1)
+    z = 0.0
+    for h0 in range(2):
+        for h1 in range(2):
+            for v0 in range(2):
+                for v1 in range(2):
+                    for bb in np.ndindex(2, 2, 2, 2, 2, 2, 2, 2):
+                        w = np.prod([b[i] for i in bb])
+                        t0, t1, l0, l1, r0, r1, d0, d1 = bb
+                        z += (w * a[t0, l0, v0, h0] * a[t1, h0, v1, r0]
+                              * a[v0, l1, d0, h1] * a[v1, h1, d1, r1])
+    assert sg == np.sign(z)
+    assert abs(lz - np.log(abs(z))) < 1e-13
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_kappa_scales_linearly():
+    A, B = synth.random_purification(2, 21)
+    a = O.double_layer(O.composite(A, B, 2))
+    b = O.boundary_vector_double_layer(2)
+    env, _ = O.ctmrg(a, 16, b, 80, tol=1e-12)
+    k0 = O.kappa(env, a)
+    env2, _ = O.ctmrg(3.0 * a, 16, b, 80, tol=1e-12)
+    assert abs(O.kappa(env2, 3.0 * a) / (3.0 * k0) - 1.0) < 1e-11
+
+
+def test_rotation_relabels_corners():
+    """CTMRG on the lattice rotated by 90 degrees: same kappa, and corner i of
+    the rotated run carries the spectrum of corner i+1 of the original (up to
+    the chi truncation, whose details depend on the move order)."""
+    a = np.abs(synth.random_site_tensor(3, 41)) + 0.5 * synth.random_site_tensor(3, 42)
+    b = np.ones(3)
+    env, _ = O.ctmrg(a, 12, b, 100, tol=1e-12)
+    ar = O.rotate(a, 1)
+    env3, _ = O.ctmrg(ar, 12, b, 100, tol=1e-12)
+    assert abs(O.kappa(env3, ar) / O.kappa(env, a) - 1.0) < 1e-11
+    s0 = O.corner_spectra(env)
+    s3 = O.corner_spectra(env3)
+    for i in range(4):
+        assert np.abs(s3[i] - s0[(i + 1) % 4]).max() < 1e-5
+        assert np.abs(s3[i] - s0[i]).max() > 1e-2
+
+
+def test_bond_metric_hermitian_and_gauge_invariant_expectation():
+    A, B = synth.random_purification(3, 31)
+    env, a, Kc, D, _ = O.environment_from_purification(A, B, 2, 18, 30, tol=1e-12)
+    E = O.bond_metric(env, a, D)
+    n = D ** 4
+    Em = E.reshape(n, n)
+    assert np.abs(Em - Em.T).max() < 1e-9 * np.abs(Em).max()
+    w = np.linalg.eigvalsh(0.5 * (Em + Em.T))
+    assert w.min() > -1e-6 * w.max()
+    # layout [ket legs u l d r][bra legs u l d r]: contracting with the
+    # composite on both sides gives <E, a> = 1, and with O in between gives <O>
+    Dk = Kc.shape[1]
+    ket = Kc.reshape(16, Dk ** 4)
+    assert abs(np.einsum('pk,kb,pb->', ket, Em, ket) - 1.0) < 1e-12
+    Hop = O.full_operator(synth.bond_operator_real(synth.random_coefficients(9)), 4)
+    val = np.einsum('qk,kb,pb,pq->', ket, Em, ket, Hop)
+    assert abs(val - O.expect(env, a, O.double_layer(Kc, Hop))) < 1e-12
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    e0 = O.expect(env, a, O.double_layer(Kc, O.full_operator(H, 4)))
+    Ag, Bg = synth.gauge_bonds(A, B, seed=8)
+    env_g, a_g, Kg, _, _ = O.environment_from_purification(Ag, Bg, 2, 18, 30, tol=1e-12)
+    e1 = O.expect(env_g, a_g, O.double_layer(Kg, O.full_operator(H, 4)))
+    # a non-orthogonal gauge changes which subspace the chi truncation keeps,
+    # so the agreement is at the truncation-error level, not at rounding level
+    assert abs(e1 - e0) < 1e-6
+    assert abs(O.kappa(env_g, a_g) / O.kappa(env, a) - 1.0) < 1e-6
