@@ -1,0 +1,194 @@
+/*
+ * ctm.h -- C ABI of the MI355X (gfx950) CTMRG environment library.
+ *
+ * What it computes (arXiv:1906.02220, Sec. III and Fig. 4): the thermal state
+ * of a hexagonal-lattice model is a purification with two sublattice tensors
+ * A and B (Fig. 3(a)).  Fusing each A-B pair across one bond type gamma gives
+ * a composite tensor on a rhombic, i.e. square, lattice (Fig. 4(b)).  The
+ * ket and bra layers of the composite are contracted into a double-layer site
+ * tensor a[u,l,d,r] with legs of dimension d = D^2 (Fig. 4(a,b)).  The corner
+ * transfer matrix renormalisation group replaces the infinite network around
+ * one site by four corner tensors C and four edge tensors T of bond dimension
+ * chi (Fig. 4(c)); the environment of the fused gamma bond then gives the
+ * full-update bond metric, the norm per site and local expectation values
+ * (Sec. III, last paragraph).
+ *
+ * Conventions.  All arrays are real IEEE double, row-major, C-contiguous.
+ *   A, B      [s=2][a=2][x][y][z]: pseudospin, ancilla, then the three bond
+ *             legs; the gamma leg has dimension D_gamma, the others D.
+ *   a         [u][l][d][r], each leg of dimension d.
+ *   environment, clockwise from the top-left: C1 T1 C2 T2 C3 T3 C4 T4.
+ *             C[a][b] (chi x chi): a on the counter-clockwise side.
+ *             T[a][m][b] (chi x d x chi): m points into the lattice.
+ *   composite physical index p = (s_A, a_A, s_B, a_B), 16 values.
+ *   double-layer leg index  = k * D + b (k ket, b bra).
+ *
+ * Memory and ownership.  Host pointers passed in are read during the call
+ * only; output buffers are caller-owned and written before return.  Device
+ * memory is allocated by the library (hipMalloc) at environment creation and
+ * released by ctm_env_destroy.  Every call on one context is serialised on
+ * the context's stream; a context is not thread-safe.
+ *
+ * Errors.  Every entry point returns a status code; nothing throws across
+ * the ABI.  The message of the last failure is kept per context and is read
+ * with ctm_last_error.  Argument errors leave the environment unchanged.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define CTM_OK        0   /* success */
+#define CTM_ENOTCONV  1   /* warning: max_sweeps reached before tol; env valid */
+#define CTM_EINVAL   -1   /* bad argument (shape, length, index, null) */
+#define CTM_ENOMEM   -2   /* device allocation failed */
+#define CTM_EDEVICE  -3   /* HIP runtime error or no usable gfx950 device */
+#define CTM_ENUMERIC -4   /* NaN/Inf in the environment or SVD failure */
+
+/* Arithmetic used for the dense contractions (projector SVD and the norm
+ * normalisation always stay in FP64). */
+#define CTM_PREC_F64     0  /* FP64 MFMA */
+#define CTM_PREC_F32     1  /* one FP32 MFMA product, FP64 storage */
+#define CTM_PREC_BF16X3  3  /* FP64 operands split into 3 BF16 slices */
+#define CTM_PREC_BF16X4  4  /* ... 4 slices */
+#define CTM_PREC_BF16X5  5  /* ... 5 slices */
+#define CTM_PREC_BF16X6  6  /* ... 6 slices */
+
+typedef struct ctm_context ctm_context;
+typedef struct ctm_env ctm_env;
+
+typedef struct ctm_opts {
+  int precision;          /* CTM_PREC_*; default CTM_PREC_F64 */
+  double eps_cut;         /* singular values below eps_cut * s_1 get S^-1/2 := 0
+                             (shapes kept); default 1e-12 */
+  int svd_block;          /* subspace size b >= chi of the truncated projector
+                             SVD; 0 = automatic (min(chi*d, chi+32, 96)) */
+  int svd_iters;          /* subspace iterations per move when warm-started;
+                             0 = automatic (2) */
+  int svd_iters_cold;     /* iterations from a random start; 0 = automatic (6) */
+  unsigned long long seed;/* seed of the counter-based generator for cold
+                             starts; default 0x5eed */
+  const double* boundary; /* length-d boundary vector of the initial edges, or
+                             NULL: e_0 for ctm_env_init_tensor, vec(I_D) for
+                             ctm_env_init_purification */
+} ctm_opts;
+
+/* Fill *opts with the defaults listed above. */
+void ctm_opts_default(ctm_opts* opts);
+
+/* Create a context on HIP device `device` (must be gfx950).  Owns one HIP
+ * stream (default priority) and the timing events.  Returns CTM_EDEVICE if
+ * the device is missing or not gfx950. */
+int ctm_context_create(int device, ctm_context** out);
+void ctm_context_destroy(ctm_context* ctx);
+/* Message of the most recent failure on this context ("" if none).  The
+ * string is owned by the context and valid until the next call on it. */
+const char* ctm_last_error(const ctm_context* ctx);
+/* Use an external HIP stream (e.g. a torch stream) for all further work of
+ * this context; NULL restores the context's own stream. */
+int ctm_context_set_stream(ctm_context* ctx, void* hip_stream);
+
+/* Environment of a user-supplied site tensor a[u][l][d][r] (d^4 doubles,
+ * host memory), chi >= 1, d >= 1.  Initial corners C = [[1]] and edges
+ * T[0,:,0] = boundary (zero-padded to chi): after k untruncated sweeps the
+ * environment is the (2k+1)^2 open lattice with that boundary vector.
+ * (Fig. 4(c): the corner and edge tensors of the square lattice.) */
+int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi,
+                        const ctm_opts* opts, ctm_env** out);
+
+/* Environment of the rhombic lattice of an A-B purification pair (Sec. III,
+ * Figs. 3(a), 4(a,b)).  Builds the composite tensor K[p,u,l,d,r] of A and B
+ * fused across bond `gamma` (0=x, 1=y, 2=z; its dimension is D_gamma, D or
+ * 4D after a gate as in Fig. 3(b)), with u = A.beta, l = A.alpha,
+ * d = B.beta, r = B.alpha where (alpha, beta) are the two other bond types in
+ * cyclic order after gamma; then the double layer a = sum_p K_p (x) K_p; then
+ * the initial environment as for ctm_env_init_tensor with boundary vec(I_D).
+ * A and B: host arrays of 4 * D * D * D_gamma doubles. */
+int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B,
+                              int D, int D_gamma, int gamma, int chi,
+                              const ctm_opts* opts, ctm_env** out);
+void ctm_env_destroy(ctm_env* env);
+
+/* CTMRG sweeps (Fig. 4(c)).  One sweep is the left, right, up and down
+ * absorption move, each built from the four enlarged corners and a
+ * projector pair from the truncated SVD of the product of the two half
+ * systems.  After every sweep delta = max over the four corners of
+ * ||s_hat - s_hat_old||_2 with s_hat the corner singular values normalised to
+ * unit 2-norm.  Stops after max_sweeps, or earlier once delta < tol when
+ * tol > 0.  sweeps_done and delta may be NULL.  Returns CTM_ENOTCONV (> 0,
+ * environment valid) if tol > 0 was not reached, CTM_ENUMERIC on NaN/Inf or
+ * an SVD failure. */
+int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double* delta);
+
+/* One absorption move: direction 0 left, 1 up, 2 right, 3 down. */
+int ctm_move(ctm_env* env, int direction);
+
+/* Norm per site of the rhombic lattice (one composite = two hexagonal
+ * sites): kappa = Z_site Z_0 / (Z_row Z_col), where Z_site closes the ring of
+ * all eight environment tensors around a, Z_0 is the ring of the corners,
+ * and Z_row (Z_col) inserts only the top and bottom (left and right) edges
+ * with their inner legs joined. */
+int ctm_norm(ctm_env* env, double* kappa);
+
+/* log|Z| and sign of the ring closed around a, with every scale divided
+ * out during the sweeps added back (the finite-lattice value for untruncated
+ * sweeps). */
+int ctm_log_z(ctm_env* env, double* log_abs, double* sign);
+
+/* Full-update bond metric of the fused gamma bond (Sec. III, last
+ * paragraph; Fig. 3(b)): the environment E of the composite site, normalised
+ * so that <E, a> = 1.  Purification environments: len must be D^8, layout
+ * [u_k][l_k][d_k][r_k][u_b][l_b][d_b][r_b] (ket legs, then bra legs).
+ * Tensor environments: len must be d^4, layout [u][l][d][r].
+ * CTM_EINVAL on a wrong len. */
+int ctm_bond_metric(ctm_env* env, double* E, size_t len);
+
+/* <O> = <psi|O|psi> / <psi|psi> for a real operator on the composite's
+ * physical index (purification environments only).  op_dim 4: op is a 4x4
+ * row-major matrix on (s_A, s_B) x (s_A', s_B') with the identity on the
+ * ancillas; op_dim 16: op is 16x16 on p = (s_A, a_A, s_B, a_B).  Real states
+ * make the imaginary part of a Hermitian operator contribute nothing, so the
+ * caller passes its real part. */
+int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value);
+
+/* <E, a_imp> / <E, a> for an impurity site tensor a_imp[u][l][d][r] (d^4
+ * doubles, host), any environment. */
+int ctm_expect_tensor(ctm_env* env, const double* a_imp, double* value);
+
+/* The four corner spectra s_hat (each normalised to unit 2-norm, descending,
+ * zero-padded): len must be 4 * chi. */
+int ctm_corner_spectra(ctm_env* env, double* s, size_t len);
+
+/* Copy the environment out / in: C 4*chi*chi, T 4*chi*d*chi (host arrays,
+ * C1..C4 then T1..T4 in the layout above), logs 8 (log scales of C1..C4,
+ * T1..T4).  ctm_env_set also resets the warm starts of the projector SVD. */
+int ctm_env_get(ctm_env* env, double* C, double* T, double* logs);
+int ctm_env_set(ctm_env* env, const double* C, const double* T, const double* logs);
+
+/* Checkpoint of the environment (C, T, logs, chi, d, sweep count) to a
+ * binary file, and restore into an environment of the same chi and d. */
+int ctm_env_save(ctm_env* env, const char* path);
+int ctm_env_load(ctm_env* env, const char* path);
+
+/* Shape queries. */
+int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps);
+
+/* Kernel timing over the calls since the last reset, measured with HIP
+ * events on the context's stream around every launch of one kernel class.
+ * cls 0: FP64 GEMMs of the n x n x n half-system and cut products;
+ * cls 1: all dense contraction kernels; cls 2: a whole move.
+ * Returns count of launches, their summed milliseconds and summed
+ * algorithmic flops.  ctm_timing_enable(ctx, 1) switches recording on. */
+int ctm_timing_enable(ctm_context* ctx, int on);
+int ctm_timing_reset(ctm_context* ctx);
+int ctm_timing_get(ctm_context* ctx, int cls, long long* count, double* ms, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTM_H */

@@ -1,0 +1,386 @@
+// C ABI of the CTMRG library (declared in include/ctm.h).  Every entry point
+// converts library errors into status codes and records the message on the
+// context; no exception crosses the ABI.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <string>
+
+#include "ctm.h"
+#include "engine.hpp"
+
+struct ctm_context {
+  ctm::Context c;
+};
+
+struct ctm_env {
+  ctm_context* owner;
+  std::unique_ptr<ctm::Env> e;
+};
+
+namespace ctm {
+
+hipEvent_t Context::get_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  CTM_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Context::resolve_timing() {
+  if (pending.empty()) return;
+  CTM_HIP(hipStreamSynchronize(stream));
+  for (auto& p : pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess && p.cls >= 0 && p.cls < 3) {
+      tcls[p.cls].count += 1;
+      tcls[p.cls].ms += ms;
+      tcls[p.cls].flops += p.flops;
+    }
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+}  // namespace ctm
+
+namespace {
+
+template <typename F>
+int guarded(ctm_context* ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->c.last_error.clear();
+    return CTM_OK;
+  } catch (const ctm::Error& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.last_error = "host allocation failed";
+    return CTM_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return CTM_EDEVICE;
+  }
+}
+
+ctm::EnvOptions to_options(const ctm_opts* o, int d) {
+  ctm::EnvOptions r;
+  if (!o) return r;
+  r.precision = o->precision;
+  r.eps_cut = o->eps_cut;
+  r.svd_block = o->svd_block;
+  r.svd_iters = o->svd_iters;
+  r.svd_iters_cold = o->svd_iters_cold;
+  r.seed = o->seed;
+  if (o->boundary) r.boundary.assign(o->boundary, o->boundary + d);
+  return r;
+}
+
+void check_precision(int p) {
+  if (p != CTM_PREC_F64 && p != CTM_PREC_F32 && !(p >= CTM_PREC_BF16X3 && p <= CTM_PREC_BF16X6))
+    throw ctm::Error(CTM_EINVAL, "unknown precision mode");
+  if (p != CTM_PREC_F64) throw ctm::Error(CTM_EINVAL, "precision mode not available in this build");
+}
+
+}  // namespace
+
+extern "C" {
+
+void ctm_opts_default(ctm_opts* o) {
+  if (!o) return;
+  o->precision = CTM_PREC_F64;
+  o->eps_cut = 1e-12;
+  o->svd_block = 0;
+  o->svd_iters = 0;
+  o->svd_iters_cold = 0;
+  o->seed = 0x5eedULL;
+  o->boundary = nullptr;
+}
+
+int ctm_context_create(int device, ctm_context** out) {
+  if (!out) return CTM_EINVAL;
+  *out = nullptr;
+  ctm_context* ctx = nullptr;
+  try {
+    ctx = new ctm_context();
+  } catch (...) {
+    return CTM_ENOMEM;
+  }
+  const int rc = guarded(ctx, [&] {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+      throw ctm::Error(CTM_EDEVICE, "no HIP device " + std::to_string(device));
+    CTM_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    CTM_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      throw ctm::Error(CTM_EDEVICE, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+    ctx->c.device = device;
+    ctx->c.num_cus = prop.multiProcessorCount;
+    CTM_HIP(hipStreamCreateWithFlags(&ctx->c.own_stream, hipStreamNonBlocking));
+    ctx->c.stream = ctx->c.own_stream;
+  });
+  if (rc != CTM_OK) {
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return CTM_OK;
+}
+
+void ctm_context_destroy(ctm_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  for (auto& p : ctx->c.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
+  ctx->c.splitk_ws.release();
+  ctx->c.scratch_small.release();
+  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.own_stream);
+  delete ctx;
+}
+
+const char* ctm_last_error(const ctm_context* ctx) {
+  return ctx ? ctx->c.last_error.c_str() : "null context";
+}
+
+int ctm_context_set_stream(ctm_context* ctx, void* s) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.stream = s ? static_cast<hipStream_t>(s) : ctx->c.own_stream;
+  });
+}
+
+int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                        ctm_env** out) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(a && out, "null argument");
+    CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
+    *out = nullptr;
+    ctm::EnvOptions o = to_options(opts, d);
+    check_precision(o.precision);
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    auto env = std::make_unique<ctm_env>();
+    env->owner = ctx;
+    env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
+    const size_t d4 = (size_t)d * d * d * d;
+    ctm::DevBuf da(d4 * sizeof(double));
+    CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+    env->e->set_site_tensor_dev(da.d());
+    env->e->init_boundary();
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    *out = env.release();
+  });
+}
+
+int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B, int D,
+                              int D_gamma, int gamma, int chi, const ctm_opts* opts,
+                              ctm_env** out) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(A && B && out, "null argument");
+    CTM_REQUIRE(D >= 1 && D_gamma >= 1 && chi >= 1, "D, D_gamma and chi must be >= 1");
+    CTM_REQUIRE(gamma >= 0 && gamma <= 2, "gamma must be 0, 1 or 2");
+    CTM_REQUIRE(D <= 16, "D above 16 is not supported");
+    *out = nullptr;
+    const int d = D * D;
+    ctm::EnvOptions o = to_options(opts, d);
+    check_precision(o.precision);
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    auto env = std::make_unique<ctm_env>();
+    env->owner = ctx;
+    env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
+    const size_t sz = 4ull * D * D * D_gamma;
+    ctm::DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double));
+    CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+    CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+    env->e->build_purification_dev(dA.d(), dB.d(), D, D_gamma, gamma);
+    env->e->init_boundary();
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    *out = env.release();
+  });
+}
+
+void ctm_env_destroy(ctm_env* env) {
+  if (!env) return;
+  (void)hipSetDevice(env->owner->c.device);
+  (void)hipStreamSynchronize(env->owner->c.stream);
+  delete env;
+}
+
+int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double* delta) {
+  if (!env) return CTM_EINVAL;
+  int status = CTM_OK;
+  const int rc = guarded(env->owner, [&] {
+    CTM_HIP(hipSetDevice(env->owner->c.device));
+    status = env->e->sweep(max_sweeps, tol, sweeps_done, delta);
+  });
+  if (rc != CTM_OK) return rc;
+  if (status != CTM_OK) env->owner->c.last_error = "max_sweeps reached before tol";
+  return status;
+}
+
+int ctm_move(ctm_env* env, int direction) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(direction >= 0 && direction <= 3, "direction must be 0..3");
+    CTM_HIP(hipSetDevice(env->owner->c.device));
+    env->e->move(direction);
+  });
+}
+
+int ctm_norm(ctm_env* env, double* kappa) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(kappa, "null argument");
+    *kappa = env->e->kappa();
+  });
+}
+
+int ctm_log_z(ctm_env* env, double* log_abs, double* sign) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(log_abs && sign, "null argument");
+    env->e->log_z(log_abs, sign);
+  });
+}
+
+int ctm_bond_metric(ctm_env* env, double* E, size_t len) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(E, "null argument");
+    env->e->bond_metric(E, len);
+  });
+}
+
+int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(op && value, "null argument");
+    *value = env->e->expect_op(op, op_dim);
+  });
+}
+
+int ctm_expect_tensor(ctm_env* env, const double* a_imp, double* value) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(a_imp && value, "null argument");
+    *value = env->e->expect_tensor(a_imp);
+  });
+}
+
+int ctm_corner_spectra(ctm_env* env, double* s, size_t len) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(s, "null argument");
+    env->e->corner_spectra(s, len);
+  });
+}
+
+int ctm_env_get(ctm_env* env, double* C, double* T, double* logs) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] { env->e->get(C, T, logs); });
+}
+
+int ctm_env_set(ctm_env* env, const double* C, const double* T, const double* logs) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(C && T && logs, "null argument");
+    env->e->set(C, T, logs);
+  });
+}
+
+static const char kMagic[8] = {'C', 'T', 'M', 'E', 'N', 'V', '0', '1'};
+
+int ctm_env_save(ctm_env* env, const char* path) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(path, "null path");
+    ctm::Env& e = *env->e;
+    std::vector<double> C(4ull * e.chi * e.chi), T(4ull * e.chi * e.d * e.chi), L(8);
+    e.get(C.data(), T.data(), L.data());
+    std::ofstream f(path, std::ios::binary);
+    CTM_REQUIRE(f.good(), std::string("cannot open ") + path);
+    const int hdr[4] = {e.chi, e.d, e.D, e.sweeps_done};
+    f.write(kMagic, 8);
+    f.write(reinterpret_cast<const char*>(hdr), sizeof(hdr));
+    f.write(reinterpret_cast<const char*>(L.data()), L.size() * sizeof(double));
+    f.write(reinterpret_cast<const char*>(C.data()), C.size() * sizeof(double));
+    f.write(reinterpret_cast<const char*>(T.data()), T.size() * sizeof(double));
+    CTM_REQUIRE(f.good(), std::string("write failed: ") + path);
+  });
+}
+
+int ctm_env_load(ctm_env* env, const char* path) {
+  if (!env) return CTM_EINVAL;
+  return guarded(env->owner, [&] {
+    CTM_REQUIRE(path, "null path");
+    ctm::Env& e = *env->e;
+    std::ifstream f(path, std::ios::binary);
+    CTM_REQUIRE(f.good(), std::string("cannot open ") + path);
+    char magic[8];
+    int hdr[4];
+    f.read(magic, 8);
+    f.read(reinterpret_cast<char*>(hdr), sizeof(hdr));
+    CTM_REQUIRE(f.good() && std::memcmp(magic, kMagic, 8) == 0, "not a checkpoint file");
+    CTM_REQUIRE(hdr[0] == e.chi && hdr[1] == e.d && hdr[2] == e.D,
+                "checkpoint shape does not match the environment");
+    std::vector<double> C(4ull * e.chi * e.chi), T(4ull * e.chi * e.d * e.chi), L(8);
+    f.read(reinterpret_cast<char*>(L.data()), L.size() * sizeof(double));
+    f.read(reinterpret_cast<char*>(C.data()), C.size() * sizeof(double));
+    f.read(reinterpret_cast<char*>(T.data()), T.size() * sizeof(double));
+    CTM_REQUIRE(f.good(), "truncated checkpoint file");
+    e.set(C.data(), T.data(), L.data());
+    e.sweeps_done = hdr[3];
+  });
+}
+
+int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps) {
+  if (!env) return CTM_EINVAL;
+  if (chi) *chi = env->e->chi;
+  if (d) *d = env->e->d;
+  if (D) *D = env->e->D;
+  if (sweeps) *sweeps = env->e->sweeps_done;
+  return CTM_OK;
+}
+
+int ctm_timing_enable(ctm_context* ctx, int on) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.resolve_timing();
+    ctx->c.timing = (on != 0);
+  });
+}
+
+int ctm_timing_reset(ctm_context* ctx) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.resolve_timing();
+    for (auto& t : ctx->c.tcls) t = ctm::TimingClass();
+  });
+}
+
+int ctm_timing_get(ctm_context* ctx, int cls, long long* count, double* ms, double* flops) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(cls >= 0 && cls < 3, "timing class must be 0, 1 or 2");
+    ctx->c.resolve_timing();
+    if (count) *count = ctx->c.tcls[cls].count;
+    if (ms) *ms = ctx->c.tcls[cls].ms;
+    if (flops) *flops = ctx->c.tcls[cls].flops;
+  });
+}
+
+}  // extern "C"

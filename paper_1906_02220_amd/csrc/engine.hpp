@@ -1,0 +1,76 @@
+// CTMRG engine: environment state and the orchestration of the absorption
+// moves, sweeps and observables on one GPU.
+#pragma once
+#include "internal.hpp"
+
+namespace ctm {
+
+struct EnvOptions {
+  int precision = 0;
+  double eps_cut = 1e-12;
+  int svd_block = 0;
+  int svd_iters = 0;
+  int svd_iters_cold = 0;
+  unsigned long long seed = 0x5eedULL;
+  std::vector<double> boundary;  // empty: default
+};
+
+class Env {
+ public:
+  Env(Context& ctx, int d, int chi, const EnvOptions& opt);
+  // classical / user site tensor (device pointer, d^4)
+  void set_site_tensor_dev(const double* a_dev);
+  // purification pair (device pointers [2][2][x][y][z])
+  void build_purification_dev(const double* A, const double* B, int D, int D_gamma, int gamma);
+  void init_boundary();
+
+  void move(int k);              // left move in the frame rotated k times
+  int sweep(int max_sweeps, double tol, int* done, double* delta);
+
+  double kappa();
+  void log_z(double* log_abs, double* sign);
+  void bond_metric(double* host_out, size_t len);
+  double expect_op(const double* op, int op_dim);
+  double expect_tensor(const double* a_imp_host);
+  void corner_spectra(double* host_out, size_t len);
+  void get(double* C, double* T, double* logs);
+  void set(const double* C, const double* T, const double* logs);
+
+  Context& ctx;
+  int d, chi, n;
+  int D = 0;          // 0: not a purification environment
+  int sweeps_done = 0;
+  EnvOptions opt;
+  int b = 0;          // subspace size of the projector SVD
+
+ private:
+  void alloc();
+  void corner(int f);
+  void svd_top(const double* Mt, int k);
+  void orth(double* Z, double* Q, int bcols);
+  void ring();
+  void reset_spectra();
+  void check_flags(const char* where);
+  const double* Cp(int i) const { return Call.d() + (size_t)(i & 3) * chi * chi; }
+  double* Cw(int i) { return Call.d() + (size_t)(i & 3) * chi * chi; }
+  const double* Tp(int i) const { return Tall.d() + (size_t)(i & 3) * chi * d * chi; }
+  double* Tw(int i) { return Tall.d() + (size_t)(i & 3) * chi * d * chi; }
+
+  DevBuf arot[4];
+  DevBuf Kc;                // composite 16 x D^4
+  DevBuf Call, Tall;        // 4 chi^2, 4 chi^2 d
+  DevBuf logs;              // 8 log scales
+  DevBuf Qb[4], X1[4];
+  bool qvalid[4] = {false, false, false, false};
+  DevBuf U, Lt, Mt, t1, t2;
+  DevBuf Om, Zb, Z0, Qz, Wv, G, Wm, Bsm, xs, ys, sv, UA, VA, winv, Pu, Pl, sm1, sm2, sm3;
+  DevBuf warm[4];
+  bool warm_ok[4] = {false, false, false, false};
+  DevBuf spec_s, spec_old, scal;  // scal: delta and observables scalars
+  DevBuf iflags;                  // [0] numeric, [1] svd, [2..] dependency flags
+  DevBuf E, E8;
+  bool e_valid = false;
+  unsigned long long rng_ctr = 0;
+};
+
+}  // namespace ctm

@@ -1,0 +1,295 @@
+// FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// C = alpha * A * B + beta * C for strided (optionally batched) operands.
+// One workgroup computes a BM x BN tile of C; its waves are arranged
+// WGM x WGN, each owning a (BM/WGM) x (BN/WGN) block made of 16x16 MFMA
+// tiles.  K advances in steps of BK through a double-buffered LDS stage:
+// while the MFMAs consume one stage, the next K tile is already loaded into
+// registers and written to the other stage, so one barrier per K tile
+// suffices.  LDS tiles are stored k-major (As[k][m], Bs[k][n]) so that the
+// 16 lanes reading one MFMA operand column touch 16 consecutive doubles.
+//
+// Operand fragments (checked on the device with an in-bounds probe):
+//   A: lane l holds A[l % 16][k0 + l / 16], B: lane l holds B[k0 + l / 16][l % 16],
+//   accumulator register r of lane l holds C[4 r + l / 16][l % 16].
+//
+// Split-K: for skinny outputs the K range is cut into `ksplit` chunks; each
+// chunk writes its partial tile to a workspace and a second kernel sums the
+// chunks in a fixed order (deterministic) and applies alpha and beta.
+#include "internal.hpp"
+
+namespace ctm {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int BK, int WGM, int WGN, bool A_KC, bool B_NC>
+__global__ __launch_bounds__(WGM * WGN * 64) void dgemm_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, long long ars,
+    long long acs, long long abs_, const double* __restrict__ B, long long brs, long long bcs,
+    long long bbs, double beta, double* __restrict__ C, long long crs, long long ccs,
+    long long cbs, int ksplit, int kchunk, double* __restrict__ W) {
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  constexpr int PAD = 2;
+  constexpr int LDA = BM + PAD, LDB = BN + PAD;
+  constexpr int LA = BM * BK / NT;  // A elements loaded per thread per K tile
+  constexpr int LB = BK * BN / NT;
+  static_assert(LA >= 1 && LB >= 1, "tile too small for the thread count");
+  static_assert(TI >= 1 && TJ >= 1, "wave tile must hold a 16x16 MFMA tile");
+  __shared__ double As[2][BK][LDA];
+  __shared__ double Bs[2][BK][LDB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave / WGN) * WM;
+  const int wn = (wave % WGN) * WN;
+  const int bz = blockIdx.z;
+  const int batch = bz / ksplit;
+  const int split = bz - batch * ksplit;
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  A += batch * abs_;
+  B += batch * bbs;
+
+  // thread -> element mapping of the global loads (coalesced along the
+  // contiguous dimension of each operand)
+  int a_r, a_k;  // first element handled: row within tile, k within tile
+  if (A_KC) {
+    constexpr int TPR = BK / LA;
+    a_r = tid / TPR;
+    a_k = (tid % TPR) * LA;
+  } else {
+    constexpr int TPK = BM / LA;
+    a_k = tid / TPK;
+    a_r = (tid % TPK) * LA;
+  }
+  int b_k, b_c;
+  if (B_NC) {
+    constexpr int TPK = BN / LB;
+    b_k = tid / TPK;
+    b_c = (tid % TPK) * LB;
+  } else {
+    constexpr int TPC = BK / LB;
+    b_c = tid / TPC;
+    b_k = (tid % TPC) * LB;
+  }
+
+  double ra[LA], rb[LB];
+  auto load_tiles = [&](int kt) {
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+      const int r = A_KC ? a_r : a_r + e;
+      const int k = A_KC ? a_k + e : a_k;
+      const int gm = m0 + r, gk = kt + k;
+      ra[e] = (gm < M && gk < kend) ? A[(long long)gm * ars + (long long)gk * acs] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int k = B_NC ? b_k : b_k + e;
+      const int c = B_NC ? b_c + e : b_c;
+      const int gk = kt + k, gn = n0 + c;
+      rb[e] = (gk < kend && gn < N) ? B[(long long)gk * brs + (long long)gn * bcs] : 0.0;
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < LA; ++e) {
+      const int r = A_KC ? a_r : a_r + e;
+      const int k = A_KC ? a_k + e : a_k;
+      As[buf][k][r] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int k = B_NC ? b_k : b_k + e;
+      const int c = B_NC ? b_c + e : b_c;
+      Bs[buf][k][c] = rb[e];
+    }
+  };
+
+  d4v acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  int buf = 0;
+  if (kbeg < kend) {
+    load_tiles(kbeg);
+    store_tiles(0);
+  }
+  __syncthreads();
+  for (int kt = kbeg; kt < kend; kt += BK) {
+    const bool more = kt + BK < kend;
+    if (more) load_tiles(kt + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) av[i] = As[buf][kk + lk][wm + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bv[j] = Bs[buf][kk + lk][wn + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store_tiles(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // epilogue
+  if (ksplit > 1) {
+    double* Wp = W + (long long)bz * M * N;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm + i * 16 + 4 * r + lk;
+          const int gn = n0 + wn + j * 16 + lr;
+          if (gm < M && gn < N) Wp[(long long)gm * N + gn] = acc[i][j][r];
+        }
+  } else {
+    double* Cp = C + batch * cbs;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm + i * 16 + 4 * r + lk;
+          const int gn = n0 + wn + j * 16 + lr;
+          if (gm < M && gn < N) {
+            double* c = Cp + (long long)gm * crs + (long long)gn * ccs;
+            const double v = alpha * acc[i][j][r];
+            *c = (beta == 0.0) ? v : v + beta * (*c);
+          }
+        }
+  }
+}
+
+// Sum of the split-K partial tiles in split order, then alpha / beta.
+__global__ void splitk_reduce_kernel(int M, int N, int ksplit, int batch, double alpha,
+                                     const double* __restrict__ W, double beta,
+                                     double* __restrict__ C, long long crs, long long ccs,
+                                     long long cbs) {
+  const long long MN = (long long)M * N;
+  const long long total = MN * batch;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long bt = idx / MN;
+    const long long rem = idx - bt * MN;
+    const int m = (int)(rem / N), n = (int)(rem - (long long)(rem / N) * N);
+    const double* w = W + bt * ksplit * MN + rem;
+    double s = 0.0;
+    for (int z = 0; z < ksplit; ++z) s += w[z * MN];
+    double* c = C + bt * cbs + (long long)m * crs + (long long)n * ccs;
+    const double v = alpha * s;
+    *c = (beta == 0.0) ? v : v + beta * (*c);
+  }
+}
+
+__global__ void scale_matrix_kernel(int M, int N, int batch, double beta, double* C,
+                                    long long crs, long long ccs, long long cbs) {
+  const long long MN = (long long)M * N;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < MN * batch;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long bt = idx / MN;
+    const long long rem = idx - bt * MN;
+    const int m = (int)(rem / N), n = (int)(rem % N);
+    double* c = C + bt * cbs + (long long)m * crs + (long long)n * ccs;
+    *c = (beta == 0.0) ? 0.0 : beta * (*c);
+  }
+}
+
+namespace {
+
+struct Cfg {
+  int BM, BN;
+};
+
+template <int BM, int BN, int BK, int WGM, int WGN>
+void launch_cfg(Context& ctx, bool akc, bool bnc, dim3 grid, int M, int N, int K, double alpha,
+                View A, View B, double beta, ViewOut C, int ksplit, int kchunk, double* W) {
+  const dim3 block(WGM * WGN * 64);
+#define CTM_LAUNCH(AK, BN_)                                                                  \
+  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, WGM, WGN, AK, BN_>), grid, block, 0,          \
+                     ctx.stream, M, N, K, alpha, A.p, A.rs, A.cs, A.bs, B.p, B.rs, B.cs, B.bs, \
+                     beta, C.p, C.rs, C.cs, C.bs, ksplit, kchunk, W)
+  if (akc && bnc) CTM_LAUNCH(true, true);
+  else if (akc && !bnc) CTM_LAUNCH(true, false);
+  else if (!akc && bnc) CTM_LAUNCH(false, true);
+  else CTM_LAUNCH(false, false);
+#undef CTM_LAUNCH
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, double beta,
+              ViewOut C, int batch, int cls) {
+  CTM_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 1, "gemm: negative size");
+  if (M == 0 || N == 0) return;
+  const double flops = 2.0 * M * N * (double)K * batch;
+  ScopedTimer t1(ctx, 1, flops);
+  ScopedTimer t0(ctx, cls == 0 ? 0 : -1, flops);
+  if (K == 0) {
+    const long long total = (long long)M * N * batch;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_matrix_kernel, dim3(blocks), dim3(256), 0, ctx.stream, M, N, batch,
+                       beta, C.p, C.rs, C.cs, C.bs);
+    CTM_HIP(hipGetLastError());
+    return;
+  }
+  // Contiguity of the operands decides the load mapping (correct either way).
+  const bool akc = (A.cs == 1);
+  const bool bnc = (B.cs == 1);
+  int BM, BN;
+  if (M >= 1024 && N >= 1024) { BM = 128; BN = 128; }
+  else if (N <= 48) { BM = 64; BN = 32; }
+  else { BM = 64; BN = 64; }
+  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+  const int BK = 16;
+  int ksplit = 1;
+  const long long target = 2LL * ctx.num_cus;
+  if (tiles < target && K >= 8 * BK) {
+    ksplit = (int)std::min<long long>((target + tiles - 1) / tiles, K / (4 * BK));
+    ksplit = std::max(1, std::min(ksplit, 64));
+  }
+  int kchunk = K;
+  double* W = nullptr;
+  if (ksplit > 1) {
+    kchunk = (K + ksplit - 1) / ksplit;
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    ksplit = (K + kchunk - 1) / kchunk;
+    const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
+    if (ctx.splitk_ws.bytes < need) {
+      CTM_HIP(hipStreamSynchronize(ctx.stream));
+      ctx.splitk_ws.alloc(need);
+    }
+    W = ctx.splitk_ws.d();
+  }
+  const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * ksplit);
+  CTM_REQUIRE(grid.y <= 65535 && grid.z <= 65535, "gemm: grid too large");
+  if (BM == 128) launch_cfg<128, 128, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
+  else if (BN == 32) launch_cfg<64, 32, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
+  else launch_cfg<64, 64, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
+  if (ksplit > 1) {
+    const long long total = (long long)M * N * batch;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, ctx.stream, M, N,
+                       ksplit, batch, alpha, W, beta, C.p, C.rs, C.cs, C.bs);
+    CTM_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace ctm

@@ -1,0 +1,183 @@
+// Internal declarations of the CTMRG library: error handling, the context,
+// and the launchers of the hand-written gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace ctm {
+
+// Error carrying one of the CTM_* status codes; converted at the C ABI.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define CTM_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      throw ::ctm::Error(-3, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+#define CTM_REQUIRE(cond, msg)                                                     \
+  do {                                                                             \
+    if (!(cond)) throw ::ctm::Error(-1, msg);                                      \
+  } while (0)
+
+// Device buffer of doubles (or raw bytes) owned by the library.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t nbytes) { alloc(nbytes); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t nbytes) {
+    release();
+    if (nbytes == 0) return;
+    if (hipMalloc(&p, nbytes) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(-2, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+    }
+    bytes = nbytes;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+  float* f() const { return static_cast<float*>(p); }
+};
+
+// Accumulated event timing per kernel class.
+struct TimingClass {
+  long long count = 0;
+  double ms = 0.0;
+  double flops = 0.0;
+};
+
+struct Context {
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  bool timing = false;
+  TimingClass tcls[3];
+  // events pending resolution: (class, start, stop, flops)
+  struct Pending { int cls; hipEvent_t a, b; double flops; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  DevBuf splitk_ws;     // split-K partial products
+  DevBuf scratch_small; // reductions and flags
+  hipEvent_t get_event();
+  void resolve_timing();
+};
+
+// Scoped timer: records an event pair around a region when timing is on.
+struct ScopedTimer {
+  Context& c;
+  int cls;
+  double flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  ScopedTimer(Context& ctx, int cls_, double fl) : c(ctx), cls(cls_), flops(fl) {
+    if (c.timing && cls >= 0) { a = c.get_event(); CTM_HIP(hipEventRecord(a, c.stream)); }
+  }
+  ~ScopedTimer() {
+    if (c.timing && a) {
+      b = c.get_event();
+      if (hipEventRecord(b, c.stream) == hipSuccess) c.pending.push_back({cls, a, b, flops});
+    }
+  }
+};
+
+// ---------------------------------------------------------------- matrices
+
+// A strided matrix view: element (i, j) of batch z is at
+// ptr[z * bs + i * rs + j * cs].
+struct View {
+  const double* p;
+  long long rs, cs, bs;
+};
+struct ViewOut {
+  double* p;
+  long long rs, cs, bs;
+};
+
+inline View rowmajor(const double* p, long long ld, long long bs = 0) { return {p, ld, 1, bs}; }
+inline View colmajor(const double* p, long long ld, long long bs = 0) { return {p, 1, ld, bs}; }
+inline ViewOut out_rowmajor(double* p, long long ld, long long bs = 0) { return {p, ld, 1, bs}; }
+
+// C = alpha * A(MxK) * B(KxN) + beta * C, FP64 MFMA, for `batch` matrices.
+// `cls` selects the timing class (-1: time only under class 1).
+void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, double beta,
+              ViewOut C, int batch = 1, int cls = -1);
+
+// Reduced-precision contractions with FP64 inputs and outputs (precision
+// mode as in ctm.h: 1 = FP32 MFMA, 3..6 = number of BF16 slices).
+void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View A, View B,
+                double beta, ViewOut C, int batch = 1, int cls = -1);
+
+// out = permutation of `in` (row-major dims[0..rank-1]); out axis a is in
+// axis perm[a].  rank <= 8.
+void permute(Context& ctx, const double* in, double* out, int rank, const long long* dims,
+             const int* perm);
+
+// ---------------------------------------------------------------- small kernels
+
+void fill_zero(Context& ctx, double* p, size_t n);
+void fill_zero_int(Context& ctx, int* p, size_t n);
+void copy_dev(Context& ctx, double* dst, const double* src, size_t n);
+// p /= max|p|; *log_slot += log(max|p|); *flag = 1 if p is not finite or all zero.
+void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag);
+// *result = sum x[i] * y[i] (fixed-order two-stage reduction, deterministic)
+void dot(Context& ctx, const double* x, const double* y, size_t n, double* result);
+// Fill count doubles with standard normal numbers from the counter-based
+// generator (SplitMix64 mixing of seed and element counter, Box-Muller).
+void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
+                 unsigned long long counter);
+// From the b x b Gram matrix G = Z^T Z of an n x b block Z: scale to unit
+// diagonal, factor the scaled Gram as R^T R (upper R), treating a column whose
+// Schur-complement pivot falls below dep_tol as dependent (its row of R is
+// set to the unit row, dep[j] = 1).  Output W = D^{-1} R^{-1} (b x b, upper),
+// so Z W has orthonormal independent columns.  *err = 1 on a non-finite G.
+void gram_cholesky(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
+                   int* err);
+// Q = Z W for an n x b row-major Z and b x b W; columns j with dep[j] != 0
+// (dep may be null) are replaced by standard normal numbers.
+void apply_right(Context& ctx, const double* Z, int ldz, const double* W, int n, int b, double* Q,
+                 int ldq, const int* dep, unsigned long long seed, unsigned long long counter);
+// One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T,
+// singular values sorted descending.  X and Y (b x b row-major) may be null
+// when only the values are wanted.  batch matrices at stride bstride.
+// *err = 1 if the sweeps did not converge or produced non-finite values.
+void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
+                int batch = 1, long long bstride = 0, long long sstride = 0);
+// Maximum b supported by jacobi_svd with vectors / values only.
+int jacobi_max_b(bool vectors);
+// w[j] = 1/sqrt(s[j]) if j < kk and s[j] > eps * s[0] > 0, else 0; j < chi.
+void inv_sqrt_cut(Context& ctx, const double* s, int kk, int chi, double eps, double* w);
+// Z[i][j] *= w[j] for an n x c block of a row-major matrix with leading dim ldz.
+void scale_cols(Context& ctx, double* Z, int n, int c, int ldz, const double* w);
+// Flip the signs of column j of X and Y (n rows, b columns) so that the entry
+// of largest magnitude of X[:, j] is positive (ties: lowest row).
+void fix_signs(Context& ctx, double* X, int ldx, double* Y, int ldy, int n, int b);
+// For 4 spectra s (4 x chi, each descending): s_hat = s / ||s||_2 per corner;
+// *delta = max_c ||s_hat_c - old_c||_2; old <- s_hat.
+void spectra_delta(Context& ctx, const double* s, double* old, int chi, double* delta);
+// out[i] = x[i] * y[i] summed over groups: res = sum_i x[i] y[i] in FP64 for
+// several vectors at once is done by dot(); traces of small products use gemm.
+
+}  // namespace ctm

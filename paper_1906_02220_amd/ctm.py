@@ -1,0 +1,319 @@
+"""Python binding of the C ABI in include/ctm.h (argument marshalling only).
+
+Every function of the header is exposed under its own name with the same
+arguments (numpy arrays for host buffers); the classes ``Context`` and
+``Environment`` wrap them for convenience.  All computation happens in the
+HIP library; if ``libctm.so`` is missing or cannot be loaded, importing the
+library raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctm.so")
+
+CTM_OK = 0
+CTM_ENOTCONV = 1
+CTM_EINVAL = -1
+CTM_ENOMEM = -2
+CTM_EDEVICE = -3
+CTM_ENUMERIC = -4
+
+CTM_PREC_F64 = 0
+CTM_PREC_F32 = 1
+CTM_PREC_BF16X3 = 3
+CTM_PREC_BF16X4 = 4
+CTM_PREC_BF16X5 = 5
+CTM_PREC_BF16X6 = 6
+
+_STATUS_NAMES = {0: "CTM_OK", 1: "CTM_ENOTCONV", -1: "CTM_EINVAL", -2: "CTM_ENOMEM",
+                 -3: "CTM_EDEVICE", -4: "CTM_ENUMERIC"}
+
+
+class CtmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class ctm_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int),
+                ("eps_cut", ctypes.c_double),
+                ("svd_block", ctypes.c_int),
+                ("svd_iters", ctypes.c_int),
+                ("svd_iters_cold", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong),
+                ("boundary", ctypes.POINTER(ctypes.c_double))]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_LL = ctypes.POINTER(ctypes.c_longlong)
+
+# name -> (restype, argtypes); mirrors include/ctm.h
+SIGNATURES = {
+    "ctm_opts_default": (None, [ctypes.POINTER(ctm_opts)]),
+    "ctm_context_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "ctm_context_destroy": (None, [_P]),
+    "ctm_last_error": (ctypes.c_char_p, [_P]),
+    "ctm_context_set_stream": (ctypes.c_int, [_P, _P]),
+    "ctm_env_init_tensor": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
+    "ctm_env_init_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
+    "ctm_env_destroy": (None, [_P]),
+    "ctm_sweep": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _I, _D]),
+    "ctm_move": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ctm_norm": (ctypes.c_int, [_P, _D]),
+    "ctm_log_z": (ctypes.c_int, [_P, _D, _D]),
+    "ctm_bond_metric": (ctypes.c_int, [_P, _D, ctypes.c_size_t]),
+    "ctm_expect": (ctypes.c_int, [_P, _D, ctypes.c_int, _D]),
+    "ctm_expect_tensor": (ctypes.c_int, [_P, _D, _D]),
+    "ctm_corner_spectra": (ctypes.c_int, [_P, _D, ctypes.c_size_t]),
+    "ctm_env_get": (ctypes.c_int, [_P, _D, _D, _D]),
+    "ctm_env_set": (ctypes.c_int, [_P, _D, _D, _D]),
+    "ctm_env_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "ctm_env_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "ctm_env_dims": (ctypes.c_int, [_P, _I, _I, _I, _I]),
+    "ctm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ctm_timing_reset": (ctypes.c_int, [_P]),
+    "ctm_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _LL, _D, _D]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libctm.so and declare every entry point; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libctm.so is not built (%s); run python -m paper_1906_02220_amd.build"
+                          % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _module_fn(name):
+    def call(*args):
+        return getattr(load_library(), name)(*args)
+    call.__name__ = name
+    call.__doc__ = "Direct call of %s (see include/ctm.h)." % name
+    return call
+
+
+for _name in SIGNATURES:
+    globals()[_name] = _module_fn(_name)
+
+
+def default_opts(**kw):
+    o = ctm_opts()
+    load_library().ctm_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "boundary":
+            continue
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One HIP device (must be gfx950) with its stream."""
+
+    def __init__(self, device=0):
+        lib = load_library()
+        h = _P()
+        rc = lib.ctm_context_create(device, ctypes.byref(h))
+        if rc != CTM_OK:
+            raise CtmError(rc, "ctm_context_create(%d) failed" % device)
+        self.h = h
+        self.lib = lib
+
+    def check(self, rc, what):
+        if rc < 0:
+            raise CtmError(rc, "%s: %s" % (what, self.lib.ctm_last_error(self.h).decode()))
+        return rc
+
+    def set_stream(self, stream_ptr):
+        self.check(self.lib.ctm_context_set_stream(self.h, _P(stream_ptr)), "set_stream")
+
+    def timing(self, on=True):
+        self.check(self.lib.ctm_timing_enable(self.h, 1 if on else 0), "timing_enable")
+
+    def timing_reset(self):
+        self.check(self.lib.ctm_timing_reset(self.h), "timing_reset")
+
+    def timing_get(self, cls):
+        c = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        fl = ctypes.c_double()
+        self.check(self.lib.ctm_timing_get(self.h, cls, ctypes.byref(c), ctypes.byref(ms),
+                                           ctypes.byref(fl)), "timing_get")
+        return c.value, ms.value, fl.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ctm_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Environment:
+    """CTMRG environment owned by the library."""
+
+    def __init__(self, ctx, handle, keep=()):
+        self.ctx = ctx
+        self.h = handle
+        self._keep = keep
+        chi = ctypes.c_int()
+        d = ctypes.c_int()
+        D = ctypes.c_int()
+        sw = ctypes.c_int()
+        ctx.lib.ctm_env_dims(self.h, ctypes.byref(chi), ctypes.byref(d), ctypes.byref(D),
+                             ctypes.byref(sw))
+        self.chi, self.d, self.D = chi.value, d.value, D.value
+
+    @staticmethod
+    def _opts(boundary, kw):
+        o = default_opts(**kw)
+        keep = ()
+        if boundary is not None:
+            bb = _f64(boundary)
+            o.boundary = _dptr(bb)
+            keep = (bb,)
+        return o, keep
+
+    @classmethod
+    def from_tensor(cls, ctx, a, chi, boundary=None, **kw):
+        a = _f64(a)
+        d = a.shape[0]
+        if a.shape != (d, d, d, d):
+            raise ValueError("a must have shape (d, d, d, d)")
+        o, keep = cls._opts(boundary, kw)
+        h = _P()
+        ctx.check(ctx.lib.ctm_env_init_tensor(ctx.h, _dptr(a), d, chi, ctypes.byref(o),
+                                              ctypes.byref(h)), "ctm_env_init_tensor")
+        return cls(ctx, h, keep)
+
+    @classmethod
+    def from_purification(cls, ctx, A, B, gamma, chi, boundary=None, **kw):
+        A = _f64(A)
+        B = _f64(B)
+        if A.shape != B.shape or A.ndim != 5 or A.shape[:2] != (2, 2):
+            raise ValueError("A and B must both have shape (2, 2, Dx, Dy, Dz)")
+        if gamma not in (0, 1, 2):
+            raise ValueError("gamma must be 0 (x), 1 (y) or 2 (z)")
+        dims = list(A.shape[2:])
+        Dg = dims[gamma]
+        rest = [dims[i] for i in range(3) if i != gamma]
+        if rest[0] != rest[1]:
+            raise ValueError("the two non-fused bonds must share one dimension D")
+        o, keep = cls._opts(boundary, kw)
+        h = _P()
+        ctx.check(ctx.lib.ctm_env_init_purification(ctx.h, _dptr(A), _dptr(B), rest[0], Dg, gamma,
+                                                    chi, ctypes.byref(o), ctypes.byref(h)),
+                  "ctm_env_init_purification")
+        return cls(ctx, h, keep)
+
+    def sweep(self, max_sweeps, tol=0.0):
+        done = ctypes.c_int()
+        delta = ctypes.c_double()
+        rc = self.ctx.check(self.ctx.lib.ctm_sweep(self.h, max_sweeps, tol, ctypes.byref(done),
+                                                   ctypes.byref(delta)), "ctm_sweep")
+        return rc, done.value, delta.value
+
+    def move(self, direction):
+        self.ctx.check(self.ctx.lib.ctm_move(self.h, direction), "ctm_move")
+
+    def norm(self):
+        k = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_norm(self.h, ctypes.byref(k)), "ctm_norm")
+        return k.value
+
+    def log_z(self):
+        la = ctypes.c_double()
+        sg = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_log_z(self.h, ctypes.byref(la), ctypes.byref(sg)),
+                       "ctm_log_z")
+        return la.value, sg.value
+
+    def bond_metric(self):
+        n = self.d ** 4
+        out = np.empty(n)
+        self.ctx.check(self.ctx.lib.ctm_bond_metric(self.h, _dptr(out), n), "ctm_bond_metric")
+        if self.D > 0:
+            return out.reshape((self.D,) * 8)
+        return out.reshape((self.d,) * 4)
+
+    def expect(self, op):
+        op = _f64(op)
+        dim = op.shape[0]
+        v = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_expect(self.h, _dptr(op), dim, ctypes.byref(v)),
+                       "ctm_expect")
+        return v.value
+
+    def expect_tensor(self, a_imp):
+        a_imp = _f64(a_imp)
+        v = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_expect_tensor(self.h, _dptr(a_imp), ctypes.byref(v)),
+                       "ctm_expect_tensor")
+        return v.value
+
+    def corner_spectra(self):
+        out = np.empty(4 * self.chi)
+        self.ctx.check(self.ctx.lib.ctm_corner_spectra(self.h, _dptr(out), out.size),
+                       "ctm_corner_spectra")
+        return out.reshape(4, self.chi)
+
+    def get(self):
+        C = np.empty((4, self.chi, self.chi))
+        T = np.empty((4, self.chi, self.d, self.chi))
+        L = np.empty(8)
+        self.ctx.check(self.ctx.lib.ctm_env_get(self.h, _dptr(C), _dptr(T), _dptr(L)),
+                       "ctm_env_get")
+        return C, T, L
+
+    def set(self, C, T, L):
+        C, T, L = _f64(C), _f64(T), _f64(L)
+        self.ctx.check(self.ctx.lib.ctm_env_set(self.h, _dptr(C), _dptr(T), _dptr(L)),
+                       "ctm_env_set")
+
+    def save(self, path):
+        self.ctx.check(self.ctx.lib.ctm_env_save(self.h, path.encode()), "ctm_env_save")
+
+    def load(self, path):
+        self.ctx.check(self.ctx.lib.ctm_env_load(self.h, path.encode()), "ctm_env_load")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.ctm_env_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

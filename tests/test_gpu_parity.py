@@ -1,0 +1,222 @@
+"""GPU parity of the HIP CTMRG path against the FP64 oracle and closed forms.
+
+Every case calls the library through its C ABI (ctypes binding) and compares
+gauge-invariant outputs: the norm per site kappa, expectation values, the
+normalised bond metric, log Z of untruncated runs, and corner spectra.
+FP64 tolerances: kappa <= 1e-10 relative, <O> <= 1e-10 absolute, normalised
+bond metric <= 1e-8 relative in Frobenius norm.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute, closed_forms as CF, ctmrg as O, gates
+from paper_1906_02220_amd import ctm, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ctm.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------ classical tensors
+
+def test_ising_onsager(ctx):
+    beta, chi = 0.4, 16
+    say("case: Ising beta=0.4 chi=16 tol=1e-10")
+    a = synth.ising_square_tensor(beta)
+    env = ctm.Environment.from_tensor(ctx, a, chi)
+    rc, done, delta = env.sweep(300, 1e-10)
+    assert rc == ctm.CTM_OK and delta < 1e-10
+    lk = np.log(env.norm())
+    assert abs(lk - CF.onsager_minus_beta_f(beta)) < 1e-11
+    oenv, _ = O.ctmrg(a, chi, O.boundary_vector_classical(2), 300, tol=1e-10)
+    assert abs(env.norm() / O.kappa(oenv, a) - 1.0) < 1e-10
+    ss = (env.expect_tensor(synth.ising_square_tensor_leg_derivative(beta, 1))
+          + env.expect_tensor(synth.ising_square_tensor_leg_derivative(beta, 3)))
+    assert abs(ss - CF.onsager_nn_correlation(beta)) < 1e-10
+
+
+@pytest.mark.parametrize("d,seed,bvec,chi,sweeps", [
+    (2, 12, (0.6, 0.8), 16, 1),
+    (2, 12, (0.6, 0.8), 16, 2),
+    (2, 12, (0.6, 0.8), 16, 3),
+])
+def test_untruncated_sweeps_equal_finite_lattice(ctx, d, seed, bvec, chi, sweeps):
+    say("case: finite lattice d=%d seed=%d chi=%d sweeps=%d" % (d, seed, chi, sweeps))
+    a = synth.random_site_tensor(d, seed)
+    b = np.array(bvec)
+    env = ctm.Environment.from_tensor(ctx, a, chi, boundary=b)
+    env.sweep(sweeps, 0.0)
+    lz, sg = env.log_z()
+    L = 2 * sweeps + 1
+    lzb, sgb = brute.finite_lattice_log_z(a, b, L, L)
+    assert sg == sgb
+    assert abs(lz - lzb) < 1e-10 * max(1.0, abs(lzb))
+
+
+def test_moves_match_oracle_move_by_move(ctx):
+    """Ragged shape (d = 3, chi = 7): every single move, in every direction,
+    leaves the same gauge-invariant kappa as the oracle's move."""
+    say("case: move-by-move d=3 chi=7")
+    a = np.abs(synth.random_site_tensor(3, 41)) + 0.5 * synth.random_site_tensor(3, 42)
+    b = np.ones(3)
+    env = ctm.Environment.from_tensor(ctx, a, 7, boundary=b)
+    oenv = O.init_env(3, 7, b)
+    arot = [O.rotate(a, k) for k in range(4)]
+    for step in range(10):
+        for k in (0, 2, 1, 3):
+            env.move(k)
+            O.left_move(oenv, arot, k, 7)
+            assert abs(env.norm() / O.kappa(oenv, a) - 1.0) < 1e-10, (step, k)
+
+
+# ------------------------------------------------------------ purification pins
+
+@pytest.mark.parametrize("gamma", [0, 1, 2])
+def test_honeycomb_ising_closed_forms(ctx, gamma):
+    say("case: honeycomb Ising gamma=%d" % gamma)
+    K = (0.3, 0.5, 0.7)
+    A, B = synth.honeycomb_ising_tensors(*K)
+    env = ctm.Environment.from_purification(ctx, A, B, gamma, 32)
+    rc, done, delta = env.sweep(300, 1e-11)
+    assert rc == ctm.CTM_OK
+    assert abs(np.log(env.norm()) - 2.0 * CF.honeycomb_minus_beta_f(*K)) < 1e-10
+    zz = np.kron(synth.SZ, synth.SZ) * 4.0
+    assert abs(env.expect(zz) - CF.honeycomb_bond_correlation(*K, which=gamma)) < 1e-10
+
+
+def test_honeycomb_padded_gauged_subspace_path(ctx):
+    """Dense D = 4 tensors of rank 2 per bond: chi * d = 256 > 96 takes the
+    subspace-iteration SVD through rank-deficient cut matrices."""
+    say("case: honeycomb padded+gauged D=4 chi=16")
+    K = 0.4
+    A, B = synth.honeycomb_ising_tensors(K, K, K)
+    A, B = synth.pad_and_gauge(A, B, 4, seed=99)
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 16)
+    env.sweep(60, 1e-11)
+    assert abs(np.log(env.norm()) - 2.0 * CF.honeycomb_minus_beta_f(K, K, K)) < 1e-9
+    zz = np.kron(synth.SZ, synth.SZ) * 4.0
+    assert abs(env.expect(zz) - CF.honeycomb_bond_correlation(K, K, K, which=2)) < 1e-9
+
+
+def test_singlets_and_single_gate(ctx):
+    say("case: singlets and one gate layer")
+    A, B = synth.singlet_tensors()
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 4)
+    env.sweep(3, 0.0)
+    assert abs(env.norm() - 1.0) < 1e-14
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    assert abs(env.expect(H) - np.trace(H) / 4.0) < 1e-14
+    tau = 0.7
+    Hg = synth.random_symmetric(4, 11)
+    A2, B2 = gates.apply_gate(A, B, gates.gate(Hg, tau), 2)
+    A2, B2 = synth.gauge_bonds(A2, B2, seed=3)
+    env2 = ctm.Environment.from_purification(ctx, A2, B2, 2, 4)
+    env2.sweep(4, 0.0)
+    op = synth.kitaev_heisenberg_bond(0.3, 1)
+    norm, ex = CF.dimer_norm_and_expectation(Hg, tau, op)
+    assert abs(env2.norm() / norm - 1.0) < 1e-12
+    assert abs(env2.expect(op) - ex) < 1e-12
+
+
+# ------------------------------------------------------------ random purifications
+
+def _compare_random(ctx, D, chi, sweeps, seed, gamma=2, D_gamma=None):
+    A, B = synth.random_purification(D, seed, D_gamma=D_gamma, gamma=gamma)
+    env = ctm.Environment.from_purification(ctx, A, B, gamma, chi)
+    env.sweep(sweeps, 0.0)
+    oenv, a, Kc, Do, _ = O.environment_from_purification(A, B, gamma, chi, sweeps)
+    k_g, k_o = env.norm(), O.kappa(oenv, a)
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    e_g = env.expect(H)
+    e_o = O.expect(oenv, a, O.double_layer(Kc, O.full_operator(H, 4)))
+    Eg = env.bond_metric()
+    Eo = O.bond_metric(oenv, a, Do)
+    s_g = env.corner_spectra()
+    s_o = np.array(O.corner_spectra(oenv))
+    return k_g, k_o, e_g, e_o, Eg, Eo, s_g, s_o
+
+
+@pytest.mark.parametrize("D,chi,sweeps,seed,gamma,Dg", [
+    (2, 12, 10, 3, 2, None),     # n = 48: direct Jacobi path
+    (3, 20, 10, 4, 1, None),     # n = 180: subspace path, ragged tiles
+    (2, 30, 8, 5, 0, 8),         # gamma bond of dimension 4D after a gate
+])
+def test_random_purification_parity(ctx, D, chi, sweeps, seed, gamma, Dg):
+    say("case: random purification D=%d chi=%d sweeps=%d seed=%d gamma=%d Dg=%s"
+        % (D, chi, sweeps, seed, gamma, Dg))
+    k_g, k_o, e_g, e_o, Eg, Eo, s_g, s_o = _compare_random(ctx, D, chi, sweeps, seed, gamma, Dg)
+    assert abs(k_g / k_o - 1.0) < 1e-10
+    assert abs(e_g - e_o) < 1e-10
+    assert np.linalg.norm(Eg - Eo) / np.linalg.norm(Eo) < 1e-8
+
+
+def test_c2_workload_parity(ctx):
+    """D = 4, chi = 32 (d = 16, chi * d = 512), seed 1234, 20 sweeps and the
+    bond metric of the fused bond."""
+    say("case: D=4 chi=32 seed=1234 20 sweeps")
+    k_g, k_o, e_g, e_o, Eg, Eo, s_g, s_o = _compare_random(ctx, 4, 32, 20, 1234)
+    say("  kappa gpu %.16g oracle %.16g" % (k_g, k_o))
+    assert abs(k_g / k_o - 1.0) < 1e-10
+    assert abs(e_g - e_o) < 1e-10
+    assert np.linalg.norm(Eg - Eo) / np.linalg.norm(Eo) < 1e-8
+    # Corner spectra depend on the gauge the projectors give the corner legs;
+    # at this seed the cut spectrum is nearly degenerate at the chi boundary
+    # (s_32/s_33 = 1.04), so the kept tail vectors of a subspace SVD and of a
+    # full SVD differ by small rotations, which moves s_hat at the 1e-9 level.
+    assert np.abs(s_g - s_o).max() < 5e-9
+
+
+def test_checkpoint_resume_is_exact(ctx, tmp_path):
+    say("case: checkpoint resume D=2 chi=12")
+    A, B = synth.random_purification(2, 9)
+    e1 = ctm.Environment.from_purification(ctx, A, B, 2, 12)
+    e1.sweep(6, 0.0)
+    e1.save(str(tmp_path / "env.bin"))
+    e1.sweep(4, 0.0)
+    e2 = ctm.Environment.from_purification(ctx, A, B, 2, 12)
+    e2.load(str(tmp_path / "env.bin"))
+    e2.sweep(4, 0.0)
+    assert e1.norm() == e2.norm()
+
+
+def test_error_paths(ctx):
+    say("case: error paths")
+    A, B = synth.random_purification(2, 9)
+    h = ctm._P()
+    o = ctm.default_opts()
+    rc = ctm.ctm_env_init_purification(ctx.h, A.ctypes.data_as(ctm._D), B.ctypes.data_as(ctm._D),
+                                       2, 2, 3, 12, ctypes.byref(o), ctypes.byref(h))
+    assert rc == ctm.CTM_EINVAL and not h.value
+    assert b"gamma" in ctm.ctm_last_error(ctx.h)
+    rc = ctm.ctm_env_init_purification(ctx.h, A.ctypes.data_as(ctm._D), B.ctypes.data_as(ctm._D),
+                                       2, 2, 2, 0, ctypes.byref(o), ctypes.byref(h))
+    assert rc == ctm.CTM_EINVAL
+    o.precision = 99
+    rc = ctm.ctm_env_init_purification(ctx.h, A.ctypes.data_as(ctm._D), B.ctypes.data_as(ctm._D),
+                                       2, 2, 2, 12, ctypes.byref(o), ctypes.byref(h))
+    assert rc == ctm.CTM_EINVAL
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 12)
+    rc, done, delta = env.sweep(1, 1e-300)
+    assert rc == ctm.CTM_ENOTCONV and done == 1
+    out = np.empty(10)
+    rc = ctm.ctm_bond_metric(env.h, out.ctypes.data_as(ctm._D), 10)
+    assert rc == ctm.CTM_EINVAL
+    Anan = A.copy()
+    Anan[0, 0, 0, 0, 0] = np.nan
+    env2 = ctm.Environment.from_purification(ctx, Anan, B, 2, 12)
+    with pytest.raises(ctm.CtmError) as ei:
+        env2.sweep(2, 0.0)
+    assert ei.value.code == ctm.CTM_ENUMERIC
