@@ -67,10 +67,10 @@ typedef struct ctm_opts {
   double eps_cut;         /* singular values below eps_cut * s_1 get S^-1/2 := 0
                              (shapes kept); default 1e-12 */
   int svd_block;          /* subspace size b >= chi of the truncated projector
-                             SVD; 0 = automatic (min(chi*d, chi+32, 96)) */
+                             SVD; 0 = automatic (min(chi*d, 96)) */
   int svd_iters;          /* subspace iterations per move when warm-started;
                              0 = automatic (2) */
-  int svd_iters_cold;     /* iterations from a random start; 0 = automatic (6) */
+  int svd_iters_cold;     /* iterations from a random start; 0 = automatic (5) */
   unsigned long long seed;/* seed of the counter-based generator for cold
                              starts; default 0x5eed */
   const double* boundary; /* length-d boundary vector of the initial edges, or
@@ -95,8 +95,9 @@ int ctm_context_set_stream(ctm_context* ctx, void* hip_stream);
 
 /* Environment of a user-supplied site tensor a[u][l][d][r] (d^4 doubles,
  * host memory), chi >= 1, d >= 1.  Initial corners C = [[1]] and edges
- * T[0,:,0] = boundary (zero-padded to chi): after k untruncated sweeps the
- * environment is the (2k+1)^2 open lattice with that boundary vector.
+ * T[0,:,0] = boundary (zero-padded to chi): after k sweeps in which no
+ * singular value of a cut matrix falls below the cutoff (nothing truncated)
+ * the environment is the (2k+1)^2 open lattice with that boundary vector.
  * (Fig. 4(c): the corner and edge tensors of the square lattice.) */
 int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi,
                         const ctm_opts* opts, ctm_env** out);

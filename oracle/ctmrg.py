@@ -141,7 +141,8 @@ def boundary_vector_classical(d):
 def init_env(d, chi, b):
     """C_i = [[1]] and T_i[0, :, 0] = b, zero-padded to chi.
 
-    After k sweeps from this start the untruncated environment is exactly the
+    After k sweeps from this start in which nothing is truncated (every cut
+    singular value above the cutoff and kept) the environment is exactly the
     (2k+1) x (2k+1) open lattice whose outer legs all end in b.
     """
     C = []

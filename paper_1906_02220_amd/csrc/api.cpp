@@ -6,20 +6,39 @@
 #include <fstream>
 #include <memory>
 #include <string>
+#include <utility>
 
 #include "ctm.h"
 #include "engine.hpp"
 
+// The context state is shared by the context handle and every environment
+// created on it, so handles may be destroyed in any order.
 struct ctm_context {
-  ctm::Context c;
+  std::shared_ptr<ctm::Context> sp;
+  ctm::Context& c;
+  ctm_context() : sp(std::make_shared<ctm::Context>()), c(*sp) {}
 };
 
 struct ctm_env {
-  ctm_context* owner;
+  std::shared_ptr<ctm::Context> owner_sp;
+  ctm::Context* owner_c;
   std::unique_ptr<ctm::Env> e;
 };
 
 namespace ctm {
+
+Context::~Context() {
+  (void)hipSetDevice(device);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+  splitk_ws.release();
+  scratch_small.release();
+  if (own_stream) (void)hipStreamDestroy(own_stream);
+}
 
 hipEvent_t Context::get_event() {
   if (!event_pool.empty()) {
@@ -53,21 +72,26 @@ void Context::resolve_timing() {
 namespace {
 
 template <typename F>
-int guarded(ctm_context* ctx, F&& f) {
+int guarded_c(ctm::Context* c, F&& f) {
   try {
     f();
-    if (ctx) ctx->c.last_error.clear();
+    if (c) c->last_error.clear();
     return CTM_OK;
   } catch (const ctm::Error& e) {
-    if (ctx) ctx->c.last_error = e.what();
+    if (c) c->last_error = e.what();
     return e.code;
   } catch (const std::bad_alloc&) {
-    if (ctx) ctx->c.last_error = "host allocation failed";
+    if (c) c->last_error = "host allocation failed";
     return CTM_ENOMEM;
   } catch (const std::exception& e) {
-    if (ctx) ctx->c.last_error = e.what();
+    if (c) c->last_error = e.what();
     return CTM_EDEVICE;
   }
+}
+
+template <typename F>
+int guarded(ctm_context* ctx, F&& f) {
+  return guarded_c(ctx ? &ctx->c : nullptr, std::forward<F>(f));
 }
 
 ctm::EnvOptions to_options(const ctm_opts* o, int d) {
@@ -136,17 +160,7 @@ int ctm_context_create(int device, ctm_context** out) {
 }
 
 void ctm_context_destroy(ctm_context* ctx) {
-  if (!ctx) return;
-  (void)hipSetDevice(ctx->c.device);
-  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
-  for (auto& p : ctx->c.pending) {
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
-  }
-  for (auto e : ctx->c.event_pool) (void)hipEventDestroy(e);
-  ctx->c.splitk_ws.release();
-  ctx->c.scratch_small.release();
-  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.own_stream);
+  // the shared state lives on while environments created on it exist
   delete ctx;
 }
 
@@ -173,7 +187,8 @@ int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi, const
     check_precision(o.precision);
     CTM_HIP(hipSetDevice(ctx->c.device));
     auto env = std::make_unique<ctm_env>();
-    env->owner = ctx;
+    env->owner_sp = ctx->sp;
+    env->owner_c = ctx->sp.get();
     env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
     const size_t d4 = (size_t)d * d * d * d;
     ctm::DevBuf da(d4 * sizeof(double));
@@ -200,7 +215,8 @@ int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B
     check_precision(o.precision);
     CTM_HIP(hipSetDevice(ctx->c.device));
     auto env = std::make_unique<ctm_env>();
-    env->owner = ctx;
+    env->owner_sp = ctx->sp;
+    env->owner_c = ctx->sp.get();
     env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
     const size_t sz = 4ull * D * D * D_gamma;
     ctm::DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double));
@@ -215,35 +231,36 @@ int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B
 
 void ctm_env_destroy(ctm_env* env) {
   if (!env) return;
-  (void)hipSetDevice(env->owner->c.device);
-  (void)hipStreamSynchronize(env->owner->c.stream);
-  delete env;
+  (void)hipSetDevice(env->owner_c->device);
+  (void)hipStreamSynchronize(env->owner_c->stream);
+  env->e.reset();
+  delete env;  // drops the environment's share of the context state
 }
 
 int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double* delta) {
   if (!env) return CTM_EINVAL;
   int status = CTM_OK;
-  const int rc = guarded(env->owner, [&] {
-    CTM_HIP(hipSetDevice(env->owner->c.device));
+  const int rc = guarded_c(env->owner_c, [&] {
+    CTM_HIP(hipSetDevice(env->owner_c->device));
     status = env->e->sweep(max_sweeps, tol, sweeps_done, delta);
   });
   if (rc != CTM_OK) return rc;
-  if (status != CTM_OK) env->owner->c.last_error = "max_sweeps reached before tol";
+  if (status != CTM_OK) env->owner_c->last_error = "max_sweeps reached before tol";
   return status;
 }
 
 int ctm_move(ctm_env* env, int direction) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(direction >= 0 && direction <= 3, "direction must be 0..3");
-    CTM_HIP(hipSetDevice(env->owner->c.device));
+    CTM_HIP(hipSetDevice(env->owner_c->device));
     env->e->move(direction);
   });
 }
 
 int ctm_norm(ctm_env* env, double* kappa) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(kappa, "null argument");
     *kappa = env->e->kappa();
   });
@@ -251,7 +268,7 @@ int ctm_norm(ctm_env* env, double* kappa) {
 
 int ctm_log_z(ctm_env* env, double* log_abs, double* sign) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(log_abs && sign, "null argument");
     env->e->log_z(log_abs, sign);
   });
@@ -259,7 +276,7 @@ int ctm_log_z(ctm_env* env, double* log_abs, double* sign) {
 
 int ctm_bond_metric(ctm_env* env, double* E, size_t len) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(E, "null argument");
     env->e->bond_metric(E, len);
   });
@@ -267,7 +284,7 @@ int ctm_bond_metric(ctm_env* env, double* E, size_t len) {
 
 int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(op && value, "null argument");
     *value = env->e->expect_op(op, op_dim);
   });
@@ -275,7 +292,7 @@ int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value) {
 
 int ctm_expect_tensor(ctm_env* env, const double* a_imp, double* value) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(a_imp && value, "null argument");
     *value = env->e->expect_tensor(a_imp);
   });
@@ -283,7 +300,7 @@ int ctm_expect_tensor(ctm_env* env, const double* a_imp, double* value) {
 
 int ctm_corner_spectra(ctm_env* env, double* s, size_t len) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(s, "null argument");
     env->e->corner_spectra(s, len);
   });
@@ -291,12 +308,12 @@ int ctm_corner_spectra(ctm_env* env, double* s, size_t len) {
 
 int ctm_env_get(ctm_env* env, double* C, double* T, double* logs) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] { env->e->get(C, T, logs); });
+  return guarded_c(env->owner_c, [&] { env->e->get(C, T, logs); });
 }
 
 int ctm_env_set(ctm_env* env, const double* C, const double* T, const double* logs) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(C && T && logs, "null argument");
     env->e->set(C, T, logs);
   });
@@ -306,7 +323,7 @@ static const char kMagic[8] = {'C', 'T', 'M', 'E', 'N', 'V', '0', '1'};
 
 int ctm_env_save(ctm_env* env, const char* path) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(path, "null path");
     ctm::Env& e = *env->e;
     std::vector<double> C(4ull * e.chi * e.chi), T(4ull * e.chi * e.d * e.chi), L(8);
@@ -325,7 +342,7 @@ int ctm_env_save(ctm_env* env, const char* path) {
 
 int ctm_env_load(ctm_env* env, const char* path) {
   if (!env) return CTM_EINVAL;
-  return guarded(env->owner, [&] {
+  return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(path, "null path");
     ctm::Env& e = *env->e;
     std::ifstream f(path, std::ios::binary);

@@ -46,12 +46,12 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
   if (n <= bmax) {
     b = n;  // the cut matrix is small enough for a direct Jacobi SVD
   } else {
-    b = opt.svd_block > 0 ? opt.svd_block : std::min(chi + 32, bmax);
+    b = opt.svd_block > 0 ? opt.svd_block : bmax;
     b = std::min(b, std::min(n, bmax));
     CTM_REQUIRE(b >= chi, "svd_block must be >= chi and <= 96 (chi <= 96 with a chi*d > 96 cut)");
   }
   if (opt.svd_iters <= 0) opt.svd_iters = 2;
-  if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 6;
+  if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 5;
   alloc();
 }
 
@@ -205,25 +205,33 @@ void Env::corner(int f) {
   qvalid[f] = true;
 }
 
-// Column-scaled CholeskyQR in two passes with dependent columns refilled by
-// random vectors between the passes: Q gets orthonormal columns spanning the
-// independent part of Z (Z is n x bcols, row-major, leading dimension b).
-void Env::orth(double* Z, double* Q, int bc) {
+// Column-scaled CholeskyQR in `passes` passes (Z is n x b row-major): the
+// Gram matrix by GEMM, its Cholesky inverse in one workgroup, Q = Z W by
+// GEMM, numerically dependent columns refilled with random vectors (which the
+// next pass orthogonalises).  Q gets orthonormal columns spanning Z.
+void Env::orth(double* Z, double* Q, int passes) {
   int* dep = (int*)iflags.p + 8;
   int* err = (int*)iflags.p + 1;
   const double* src = Z;
-  for (int pass = 0; pass < 2; ++pass) {
-    double* dst = (pass == 0) ? Wv.d() : Q;
-    gemm_f64(ctx, bc, bc, n, 1.0, colmajor(src, b), rowmajor(src, b), 0.0, out_rowmajor(G.d(), bc));
-    gram_cholesky(ctx, G.d(), bc, 1e-12, Wm.d(), dep, err);
-    apply_right(ctx, src, b, Wm.d(), n, bc, dst, b, dep, opt.seed, rng_ctr);
-    rng_ctr += (unsigned long long)n * bc;
+  for (int pass = 0; pass < passes; ++pass) {
+    double* dst = (pass == passes - 1) ? Q : ((pass & 1) ? Zb.d() : Wv.d());
+    if (dst == src) dst = (src == Wv.d()) ? Zb.d() : Wv.d();
+    gemm_f64(ctx, b, b, n, 1.0, colmajor(src, b), rowmajor(src, b), 0.0, out_rowmajor(G.d(), b));
+    chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err);
+    gemm_f64(ctx, n, b, b, 1.0, rowmajor(src, b), rowmajor(Wm.d(), b), 0.0, out_rowmajor(dst, b));
+    refill_columns(ctx, dst, b, n, b, dep, opt.seed, rng_ctr);
+    rng_ctr += (unsigned long long)n * b;
     src = dst;
   }
 }
 
-// a6: top-chi singular triplets of M = Mt^T.  Left vectors of Mt (= Y of M)
-// go to UA, right vectors (= X of M) to VA, values to sv; n x b row-major.
+// a6: top-chi singular triplets of M = Mt^T by subspace iteration on the
+// warm start of the previous move in the same direction.  Left vectors of
+// Mt (= Y of M) go to UA, right vectors (= X of M) to VA, values to sv;
+// n x b row-major.  One iteration: Z = orth(Mt Om), Om <- orth(Mt^T Z);
+// then the Rayleigh-Ritz step: Z = Mt Om, Qz = orth(Z),
+// B = Qz^T Z (upper triangular), B = x s y^T by one-sided Jacobi on B^T,
+// UA = Qz x, VA = Om y.
 void Env::svd_top(const double* MtP, int k) {
   int* err = (int*)iflags.p + 1;
   if (n <= jacobi_max_b(true)) {
@@ -235,24 +243,27 @@ void Env::svd_top(const double* MtP, int k) {
   if (warm_ok[k]) {
     copy_dev(ctx, Om.d(), warm[k].d(), (size_t)n * b);
   } else {
-    fill_normal(ctx, Zb.d(), (size_t)n * b, opt.seed, rng_ctr);
+    fill_normal(ctx, Z0.d(), (size_t)n * b, opt.seed, rng_ctr);
     rng_ctr += (unsigned long long)n * b;
-    orth(Zb.d(), Om.d(), b);
+    orth(Z0.d(), Om.d(), 2);
     iters = opt.svd_iters_cold;
   }
   for (int it = 0; it < iters; ++it) {
-    gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Zb.d(), b));
-    orth(Zb.d(), Qz.d(), b);
-    gemm_f64(ctx, n, b, n, 1.0, colmajor(MtP, n), rowmajor(Qz.d(), b), 0.0, out_rowmajor(Zb.d(), b));
-    orth(Zb.d(), Om.d(), b);
+    // Z = Mt Om must be orthogonalised (not only normalised) before Mt^T is
+    // applied: a column carrying a small contamination of a leading
+    // direction would otherwise lose its own small-singular-value component.
+    gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+    orth(Z0.d(), Qz.d(), 1);
+    gemm_f64(ctx, n, b, n, 1.0, colmajor(MtP, n), rowmajor(Qz.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+    orth(Z0.d(), Om.d(), 2);
   }
-  // Rayleigh-Ritz: Z0 = Mt Om = Qz B, B = Qz^T Z0
+  // Rayleigh-Ritz
   gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
-  orth(Z0.d(), Qz.d(), b);
+  orth(Z0.d(), Qz.d(), 2);
   gemm_f64(ctx, b, b, n, 1.0, colmajor(Qz.d(), b), rowmajor(Z0.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
-  jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err);
-  apply_right(ctx, Qz.d(), b, xs.d(), n, b, UA.d(), b, nullptr, 0, 0);
-  apply_right(ctx, Om.d(), b, ys.d(), n, b, VA.d(), b, nullptr, 0, 0);
+  jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, true);
+  gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
+  gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
   fix_signs(ctx, UA.d(), b, VA.d(), b, n, b);
   copy_dev(ctx, warm[k].d(), VA.d(), (size_t)n * b);
   warm_ok[k] = true;

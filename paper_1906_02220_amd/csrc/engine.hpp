@@ -47,7 +47,7 @@ class Env {
   void alloc();
   void corner(int f);
   void svd_top(const double* Mt, int k);
-  void orth(double* Z, double* Q, int bcols);
+  void orth(double* Z, double* Q, int passes);
   void ring();
   void reset_spectra();
   void check_flags(const char* where);

@@ -82,6 +82,10 @@ struct Context {
   std::vector<hipEvent_t> event_pool;
   DevBuf splitk_ws;     // split-K partial products
   DevBuf scratch_small; // reductions and flags
+  Context() = default;
+  Context(const Context&) = delete;
+  Context& operator=(const Context&) = delete;
+  ~Context();
   hipEvent_t get_event();
   void resolve_timing();
 };
@@ -148,23 +152,27 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
 // generator (SplitMix64 mixing of seed and element counter, Box-Muller).
 void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
                  unsigned long long counter);
-// From the b x b Gram matrix G = Z^T Z of an n x b block Z: scale to unit
-// diagonal, factor the scaled Gram as R^T R (upper R), treating a column whose
-// Schur-complement pivot falls below dep_tol as dependent (its row of R is
-// set to the unit row, dep[j] = 1).  Output W = D^{-1} R^{-1} (b x b, upper),
-// so Z W has orthonormal independent columns.  *err = 1 on a non-finite G.
-void gram_cholesky(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                   int* err);
-// Q = Z W for an n x b row-major Z and b x b W; columns j with dep[j] != 0
-// (dep may be null) are replaced by standard normal numbers.
-void apply_right(Context& ctx, const double* Z, int ldz, const double* W, int n, int b, double* Q,
-                 int ldq, const int* dep, unsigned long long seed, unsigned long long counter);
+// From the b x b Gram matrix G = Z^T Z of an n x b block Z (b <= 96):
+// W = D^-1 R^-1 with D = sqrt(diag G) and R^T R = D^-1 G D^-1 (upper R), so
+// that Z W has orthonormal columns.  A column whose Schur-complement pivot
+// falls below dep_tol is dependent: it takes no part in the elimination and
+// dep[j] = 1 (its column of Z W must be replaced).  *err = 1 on non-finite G.
+void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
+                  int* err);
+// Replace the columns j with dep[j] != 0 of an n x b row-major Q by standard
+// normal numbers from the counter-based generator.
+void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
+                    unsigned long long seed, unsigned long long counter);
+// Scale every column of an n x b row-major Z to unit 2-norm.
+void normalise_columns(Context& ctx, double* Z, int ldz, int n, int b);
 // One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T,
 // singular values sorted descending.  X and Y (b x b row-major) may be null
-// when only the values are wanted.  batch matrices at stride bstride.
-// *err = 1 if the sweeps did not converge or produced non-finite values.
+// when only the values are wanted.  batch matrices at stride bstride.  With
+// trans the rotations act on the columns of B^T (faster for a graded upper
+// triangular B).  *err = 1 if the sweeps did not converge or produced
+// non-finite values.
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
-                int batch = 1, long long bstride = 0, long long sstride = 0);
+                int batch = 1, long long bstride = 0, long long sstride = 0, bool trans = false);
 // Maximum b supported by jacobi_svd with vectors / values only.
 int jacobi_max_b(bool vectors);
 // w[j] = 1/sqrt(s[j]) if j < kk and s[j] > eps * s[0] > 0, else 0; j < chi.
@@ -177,7 +185,5 @@ void fix_signs(Context& ctx, double* X, int ldx, double* Y, int ldy, int n, int 
 // For 4 spectra s (4 x chi, each descending): s_hat = s / ||s||_2 per corner;
 // *delta = max_c ||s_hat_c - old_c||_2; old <- s_hat.
 void spectra_delta(Context& ctx, const double* s, double* old, int chi, double* delta);
-// out[i] = x[i] * y[i] summed over groups: res = sum_i x[i] y[i] in FP64 for
-// several vectors at once is done by dot(); traces of small products use gemm.
 
 }  // namespace ctm

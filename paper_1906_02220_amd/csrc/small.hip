@@ -3,6 +3,7 @@
 // orthonormalise the subspace of the truncated projector SVD, the one-sided
 // Jacobi SVD of small square matrices, and column scalings.
 #include <cfloat>
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -28,6 +29,24 @@ __device__ inline double normal_at(unsigned long long seed, unsigned long long k
   const double u1 = ((double)(x1 >> 11) + 1.0) * (1.0 / 9007199254740992.0);  // (0, 1]
   const double u2 = (double)(x2 >> 11) * (1.0 / 9007199254740992.0);          // [0, 1)
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// Reciprocal and reciprocal square root of a normal, finite double: the
+// hardware estimate refined by two Newton steps (full double precision).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * r, r, 0.5);
+  r = fma(r, e, r);
+  e = fma(-h * r, r, 0.5);
+  return fma(r, e, r);
 }
 
 template <typename T>
@@ -134,191 +153,272 @@ __global__ void sum_final_kernel(const double* partial, int nb, double* out) {
 
 // ------------------------------------------------------------ Gram-Cholesky
 
-__global__ __launch_bounds__(1024) void gram_cholesky_kernel(const double* __restrict__ G, int b,
-                                                             double dep_tol,
-                                                             double* __restrict__ Wout,
-                                                             int* __restrict__ dep, int* err) {
-  extern __shared__ double lds[];
-  double* R = lds;              // b x b, row-major; upper part R, lower part X^T
-  double* D = lds + b * b;      // column scales
-  double* Xd = D + b;           // diagonal of X = R^{-1}
-  int* depl = (int*)(Xd + b);   // dependency flags
+// Cholesky factor and its inverse in one pass, register-tiled: 256 threads as
+// a 16 x 16 grid, thread (ti, tj) owning entries (ti + 16 r, tj + 16 c),
+// r, c < 6, of the symmetric Schur complement S and of X (both 96 x 96,
+// zero beyond b so that no row or column needs a guard).  Step k eliminates
+// column k below the pivot (S -= s_k s_k^T / piv on the trailing block) and
+// applies the same row operation to X, then scales row k of X by 1/sqrt(piv).
+// At the end X = R^-T, where R^T R is the column-scaled Gram matrix, so
+// W = D^-1 X^T has Z W orthonormal.  Columns whose pivot falls below dep_tol
+// (numerically dependent) are skipped: no elimination, flag set.  All
+// updates are unconditional FMAs with masked multipliers.
+__global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict__ G, int b,
+                                                       double dep_tol, double* __restrict__ Wout,
+                                                       int* __restrict__ dep, int* err) {
+  __shared__ double Dn[96];
+  __shared__ double rowk[96];
+  __shared__ double xrow[96];
+  __shared__ int depl[96];
   __shared__ int bad;
   const int t = threadIdx.x;
-  const int nt = blockDim.x;
+  const int ti = t >> 4, tj = t & 15;
   if (t == 0) bad = 0;
-  for (int i = t; i < b; i += nt) {
-    const double g = G[i * b + i];
-    D[i] = (g > 0.0 && isfinite(g)) ? sqrt(g) : 0.0;
-    if (!isfinite(g)) bad = 1;
+  if (t < 96) {
+    double dv = 0.0;
+    if (t < b) {
+      const double g = G[t * b + t];
+      dv = (g > 0.0 && isfinite(g)) ? sqrt(g) : 0.0;
+    }
+    Dn[t] = dv;
   }
   __syncthreads();
-  for (int idx = t; idx < b * b; idx += nt) {
-    const int i = idx / b, j = idx - (idx / b) * b;
-    const double g = G[idx];
-    if (!isfinite(g)) bad = 1;
-    const double den = D[i] * D[j];
-    R[idx] = (den > 0.0) ? g / den : 0.0;
-  }
-  __syncthreads();
-  // right-looking upper Cholesky of the unit-diagonal Gram with dependency
-  // detection (a pivot below dep_tol marks the column as dependent)
+  double S[6][6], X[6][6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ti + 16 * r, j = tj + 16 * c;
+      double v = 0.0;
+      if (i < b && j < b) {
+        const double g = G[i * b + j];
+        if (!isfinite(g)) bad = 1;
+        const double den = Dn[i] * Dn[j];
+        v = den > 0.0 ? g / den : 0.0;
+      }
+      S[r][c] = v;
+      X[r][c] = (i == j) ? 1.0 : 0.0;
+    }
   for (int k = 0; k < b; ++k) {
-    const double piv = R[k * b + k];
-    const bool dk = !(piv > dep_tol);
-    const double r = dk ? 1.0 : sqrt(piv);
-    __syncthreads();
-    if (t == 0) depl[k] = dk ? 1 : 0;
-    for (int j = k + 1 + t; j < b; j += nt) R[k * b + j] = dk ? 0.0 : R[k * b + j] / r;
-    if (t == 0) R[k * b + k] = r;
-    __syncthreads();
-    const int m = b - k - 1;
-    if (!dk && m > 0) {
-      for (int idx = t; idx < m * m; idx += nt) {
-        const int i = k + 1 + idx / m, j = k + 1 + (idx - (idx / m) * m);
-        if (j >= i) R[i * b + j] -= R[k * b + i] * R[k * b + j];
+    const int rk = k >> 4;
+    if (ti == (k & 15)) {
+      // row k of S and X, selected from the owning register row without
+      // dynamic indexing
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        double sv = S[0][c], xv = X[0][c];
+#pragma unroll
+        for (int r = 1; r < 6; ++r) {
+          sv = (rk == r) ? S[r][c] : sv;
+          xv = (rk == r) ? X[r][c] : xv;
+        }
+        rowk[tj + 16 * c] = sv;
+        xrow[tj + 16 * c] = xv;
       }
     }
     __syncthreads();
-  }
-  // X = R^{-1}: thread j computes column j; X[i][j] (i < j) is kept at R[j][i]
-  for (int j = t; j < b; j += nt) {
-    const double xjj = 1.0 / R[j * b + j];
-    Xd[j] = xjj;
-    for (int i = j - 1; i >= 0; --i) {
-      double s = R[i * b + j] * xjj;
-      for (int k = i + 1; k < j; ++k) s += R[i * b + k] * R[j * b + k];
-      R[j * b + i] = -s / R[i * b + i];
+    const double piv = rowk[k];
+    const bool dk = !(piv > dep_tol);
+    const double ir = dk ? 1.0 : rsq_nr(piv);
+    const double ipiv = dk ? 0.0 : ir * ir;
+    double xr[6], sr[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int j = tj + 16 * c;
+      xr[c] = xrow[j];
+      sr[c] = (j > k) ? rowk[j] : 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const int i = ti + 16 * r;
+      const double mi = (i > k) ? rowk[i] * ipiv : 0.0;
+      const double sc = (i == k) ? ir : 1.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        S[r][c] = fma(-mi, sr[c], S[r][c]);
+        X[r][c] = fma(-mi, xr[c], X[r][c]) * sc;
+      }
+    }
+    if (t == 0) depl[k] = dk ? 1 : 0;
+    __syncthreads();
   }
-  __syncthreads();
-  // W = D^{-1} X (row i scaled by 1/D_i; zero column scale -> zero row)
-  for (int idx = t; idx < b * b; idx += nt) {
-    const int i = idx / b, j = idx - (idx / b) * b;
-    double x = 0.0;
-    if (i == j) x = Xd[i];
-    else if (i < j) x = R[j * b + i];
-    Wout[idx] = (D[i] > 0.0) ? x / D[i] : 0.0;
-  }
-  for (int i = t; i < b; i += nt) dep[i] = depl[i];
+  // W[j][i] = X[i][j] / D[j]
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ti + 16 * r, j = tj + 16 * c;
+      if (i < b && j < b) Wout[j * b + i] = Dn[j] > 0.0 ? X[r][c] / Dn[j] : 0.0;
+    }
+  if (t < b) dep[t] = depl[t];
   if (t == 0 && bad) *err = 1;
 }
 
-// Q = Z W with W staged in LDS; dependent columns refilled with normals.
-__global__ __launch_bounds__(256) void apply_right_kernel(const double* __restrict__ Z, int ldz,
-                                                          const double* __restrict__ Wm, int n,
-                                                          int b, double* __restrict__ Q, int ldq,
-                                                          const int* __restrict__ dep,
-                                                          unsigned long long seed,
-                                                          unsigned long long ctr) {
-  extern __shared__ double Ws[];
-  const int t = threadIdx.x;
-  for (int idx = t; idx < b * b; idx += blockDim.x) Ws[idx] = Wm[idx];
+// Replace the columns j with dep[j] != 0 of an n x b row-major Q by
+// standard normal numbers.
+__global__ void refill_kernel(double* Q, int ldq, int n, int b, const int* __restrict__ dep,
+                              unsigned long long seed, unsigned long long ctr) {
+  __shared__ int dl[128];
+  for (int j = threadIdx.x; j < b; j += blockDim.x) dl[j] = dep[j];
   __syncthreads();
-  constexpr int TPR = 16;  // threads per row
-  const int row = blockIdx.x * (256 / TPR) + t / TPR;
-  const int cg = t % TPR;
-  if (row >= n) return;
-  const double* z = Z + (long long)row * ldz;
-  double acc[8];
-  for (int c0 = 0; c0 < b; c0 += 8 * TPR) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) acc[e] = 0.0;
-    for (int k = 0; k < b; ++k) {
-      const double zk = z[k];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = c0 + cg + e * TPR;
-        if (j < b) acc[e] += zk * Ws[k * b + j];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int j = c0 + cg + e * TPR;
-      if (j < b) {
-        double v = acc[e];
-        if (dep && dep[j]) v = normal_at(seed, ctr + (unsigned long long)row * b + j);
-        Q[(long long)row * ldq + j] = v;
-      }
+  const long long total = (long long)n * b;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(idx % b);
+    if (dl[j]) {
+      const long long i = idx / b;
+      Q[i * ldq + j] = normal_at(seed, ctr + (unsigned long long)idx);
     }
   }
+}
+
+// Scale every column of an n x b row-major Z to unit 2-norm (one block per
+// column, zero columns left as they are).
+__global__ void normalise_cols_kernel(double* Z, int ldz, int n) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = Z[(long long)i * ldz + j];
+    s += v * v;
+  }
+  s = block_sum256(s, sh);
+  const double f = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  if (s > 0.0)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) Z[(long long)i * ldz + j] *= f;
 }
 
 // ------------------------------------------------------------ Jacobi SVD
 
-// One workgroup per matrix.  Columns of the working matrix and of V are kept
-// column-major in LDS; each round of the circle schedule rotates bp/2
-// disjoint column pairs in parallel, a group of TP lanes per pair.
-__global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* __restrict__ Bm, int b,
-                                                          long long bstride, long long sstride,
-                                                          double* __restrict__ Xo,
-                                                          double* __restrict__ so,
-                                                          double* __restrict__ Yo, int* err,
-                                                          int want_vec, int TP) {
+// Sum over a group of 8 consecutive lanes (half a DPP row): butterflies
+// with quad permutations, then the half-row mirror.
+__device__ inline double dpp_step(double x, int ctrl) {
+  const long long u = __double_as_longlong(x);
+  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+  if (ctrl == 0) {
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  } else if (ctrl == 1) {
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+  }
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline double lane8_sum(double v) {
+  v += dpp_step(v, 0);
+  v += dpp_step(v, 1);
+  v += dpp_step(v, 2);
+  return v;
+}
+
+// One workgroup per matrix, one-sided Jacobi (Hestenes) on the columns of A
+// (A = B, or B^T when trans != 0).  Columns of the working matrix and of V
+// are kept column-major in LDS with an odd stride; each round of the circle
+// schedule (precomputed in LDS) rotates the bp/2 disjoint column pairs in
+// parallel, 8 lanes per pair, each lane holding RPT rows of the pair in
+// registers.  The rotation (the smaller root t of t^2 + 2 zeta t - 1 = 0,
+// c = 1/sqrt(1 + t^2), s = c t) uses Newton-refined reciprocals.  On exit
+// A = U diag(s) V^T with s descending; with trans == 0 X = U, Y = V, with
+// trans != 0 X = V, Y = U (so that always B = X diag(s) Y^T).
+template <int RPT>
+__global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restrict__ Bm, int b,
+                                                         long long bstride, long long sstride,
+                                                         double* __restrict__ Xo,
+                                                         double* __restrict__ so,
+                                                         double* __restrict__ Yo, int* err,
+                                                         int want_vec, int trans) {
   extern __shared__ double lds[];
   const int bp = b + (b & 1);
-  double* Wc = lds;                                 // bp columns of length b
-  double* Vc = want_vec ? lds + bp * b : nullptr;   // bp columns of length b
-  double* sv = lds + (want_vec ? 2 : 1) * bp * b;   // bp singular values
+  constexpr int ld = 8 * RPT + 1;  // odd stride, rows b..8*RPT-1 stay zero
+  double* Wc = lds;                                  // bp columns
+  double* Vc = want_vec ? lds + bp * ld : nullptr;   // bp columns
+  double* sv = lds + (want_vec ? 2 : 1) * bp * ld;   // bp singular values
+  unsigned char* sched = (unsigned char*)(sv + bp);  // (bp-1) rounds x bp entries
   __shared__ int changed;
   __shared__ int bad;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   const double* B = Bm + blockIdx.x * bstride;
   if (t == 0) { changed = 0; bad = 0; }
-  for (int idx = t; idx < bp * b; idx += nt) {
-    const int j = idx / b, i = idx - (idx / b) * b;
-    Wc[idx] = (j < b) ? B[(long long)i * b + j] : 0.0;
-    if (Vc) Vc[idx] = (i == j) ? 1.0 : 0.0;
+  for (int idx = t; idx < bp * ld; idx += nt) {
+    const int j = idx / ld, i = idx - (idx / ld) * ld;
+    double v = 0.0;
+    if (j < b && i < b) v = trans ? B[(long long)j * b + i] : B[(long long)i * b + j];
+    Wc[idx] = v;
+    if (Vc) Vc[idx] = (i == j && i < b) ? 1.0 : 0.0;
   }
-  __syncthreads();
   const int P = bp / 2;
   const int m = bp - 1;
-  const int pi = t / TP;
-  const int sub = t - pi * TP;
-  const double tol = fmax(1e-15, sqrt((double)b) * DBL_EPSILON);
+  for (int idx = t; idx < m * P; idx += nt) {
+    const int r = idx / P, pi = idx - (idx / P) * P;
+    int p, q;
+    if (pi == 0) { p = m; q = r; }
+    else { p = (r + pi) % m; q = (r - pi + m) % m; }
+    sched[2 * idx] = (unsigned char)p;
+    sched[2 * idx + 1] = (unsigned char)q;
+  }
+  __syncthreads();
+  const int pi = t >> 3;
+  const int sub = t & 7;
+  const bool active = pi < P;
+  const double tol = b * DBL_EPSILON;
+  const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
     for (int r = 0; r < m; ++r) {
-      if (pi < P) {
-        int p, q;
-        if (pi == 0) { p = m; q = r; }
-        else { p = (r + pi) % m; q = (r - pi + m) % m; }
-        double* wp = Wc + p * b;
-        double* wq = Wc + q * b;
+      if (active) {
+        const int p = sched[2 * (r * P + pi)];
+        const int q = sched[2 * (r * P + pi) + 1];
+        double* wp = Wc + p * ld + sub;
+        double* wq = Wc + q * ld + sub;
+        double xp[RPT], xq[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          xp[k] = wp[8 * k];
+          xq[k] = wq[8 * k];
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = sub; i < b; i += TP) {
-          const double x = wp[i], y = wq[i];
-          al += x * x; be += y * y; ga += x * y;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          al = fma(xp[k], xp[k], al);
+          be = fma(xq[k], xq[k], be);
+          ga = fma(xp[k], xq[k], ga);
         }
-        for (int o = TP / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, TP);
-          be += __shfl_xor(be, o, TP);
-          ga += __shfl_xor(ga, o, TP);
-        }
-        double tt = 0.0;
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          // tangent of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0
-          const double zeta = (be - al) / (2.0 * ga);
-          tt = (fabs(zeta) < 1e150)
-                   ? (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta))
-                   : 0.5 / zeta;
-        }
+        al = lane8_sum(al);
+        be = lane8_sum(be);
+        ga = lane8_sum(ga);
+        const bool rot = al > 0.0 && be > 0.0 && ga * ga > tol2 * al * be;
+        // rotation parameters, computed unconditionally (c = 1, s = 0 when idle)
+        const double g2 = rot ? 2.0 * ga : 1.0;
+        const double zeta = rot ? (be - al) * rcp_nr(g2) : 0.0;
+        const double az = fmin(fabs(zeta), 1e150);
+        const double w = fma(az, az, 1.0);
+        double tt = rcp_nr(az + w * rsq_nr(w));   // 1 / (|zeta| + sqrt(1 + zeta^2))
+        tt = rot ? (zeta < 0.0 ? -tt : tt) : 0.0;
         if (tt != 0.0) {
-          const double c = 1.0 / sqrt(1.0 + tt * tt);
+          const double c = rsq_nr(fma(tt, tt, 1.0));
           const double s = c * tt;
-          for (int i = sub; i < b; i += TP) {
-            const double x = wp[i], y = wq[i];
-            wp[i] = c * x - s * y;
-            wq[i] = s * x + c * y;
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            wp[8 * k] = c * xp[k] - s * xq[k];
+            wq[8 * k] = s * xp[k] + c * xq[k];
           }
           if (Vc) {
-            double* vp = Vc + p * b;
-            double* vq = Vc + q * b;
-            for (int i = sub; i < b; i += TP) {
-              const double x = vp[i], y = vq[i];
-              vp[i] = c * x - s * y;
-              vq[i] = s * x + c * y;
+            double* vp = Vc + p * ld + sub;
+            double* vq = Vc + q * ld + sub;
+            double yp[RPT], yq[RPT];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+              yp[k] = vp[8 * k];
+              yq[k] = vq[8 * k];
+            }
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+              vp[8 * k] = c * yp[k] - s * yq[k];
+              vq[8 * k] = s * yp[k] + c * yq[k];
             }
           }
           if (sub == 0) changed = 1;
@@ -335,13 +435,15 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* __restri
   // singular values and ordering
   for (int j = t; j < bp; j += nt) {
     double s = 0.0;
-    for (int i = 0; i < b; ++i) s += Wc[j * b + i] * Wc[j * b + i];
+    for (int i = 0; i < b; ++i) s += Wc[j * ld + i] * Wc[j * ld + i];
     s = sqrt(s);
     if (!isfinite(s)) bad = 1;
     sv[j] = s;
   }
   __syncthreads();
   double* so_b = so + blockIdx.x * sstride;
+  double* Uo = trans ? Yo : Xo;   // normalised columns of the working matrix
+  double* Vo = trans ? Xo : Yo;   // accumulated rotations
   for (int j = t; j < b; j += nt) {
     const double sj = sv[j];
     int rank = 0;
@@ -350,14 +452,14 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(const double* __restri
       rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
     }
     so_b[rank] = sj;
-    if (Xo) {
-      double* X = Xo + blockIdx.x * bstride;
+    if (Uo) {
+      double* X = Uo + blockIdx.x * bstride;
       const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-      for (int i = 0; i < b; ++i) X[(long long)i * b + rank] = Wc[j * b + i] * inv;
+      for (int i = 0; i < b; ++i) X[(long long)i * b + rank] = Wc[j * ld + i] * inv;
     }
-    if (Yo && Vc) {
-      double* Y = Yo + blockIdx.x * bstride;
-      for (int i = 0; i < b; ++i) Y[(long long)i * b + rank] = Vc[j * b + i];
+    if (Vo && Vc) {
+      double* Y = Vo + blockIdx.x * bstride;
+      for (int i = 0; i < b; ++i) Y[(long long)i * b + rank] = Vc[j * ld + i];
     }
   }
   if (t == 0 && (bad || sweep >= 60)) *err = 1;
@@ -506,41 +608,53 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
   CTM_HIP(hipGetLastError());
 }
 
-void gram_cholesky(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                   int* err) {
-  CTM_REQUIRE(b >= 1 && b <= 128, "gram_cholesky: b out of range");
-  const size_t lds = (size_t)b * b * sizeof(double) + 2 * b * sizeof(double) + b * sizeof(int);
-  allow_lds((const void*)gram_cholesky_kernel, lds);
-  hipLaunchKernelGGL(gram_cholesky_kernel, dim3(1), dim3(1024), lds, ctx.stream, G, b, dep_tol, W,
-                     dep, err);
-  CTM_HIP(hipGetLastError());
-}
-
-void apply_right(Context& ctx, const double* Z, int ldz, const double* W, int n, int b, double* Q,
-                 int ldq, const int* dep, unsigned long long seed, unsigned long long counter) {
-  CTM_REQUIRE(b >= 1 && b <= 128, "apply_right: b out of range");
-  const size_t lds = (size_t)b * b * sizeof(double);
-  allow_lds((const void*)apply_right_kernel, lds);
-  const int blocks = (n + 15) / 16;
-  hipLaunchKernelGGL(apply_right_kernel, dim3(blocks), dim3(256), lds, ctx.stream, Z, ldz, W, n, b,
-                     Q, ldq, dep, seed, counter);
-  CTM_HIP(hipGetLastError());
-}
-
 int jacobi_max_b(bool vectors) { return vectors ? 96 : 128; }
 
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
-                int batch, long long bstride, long long sstride) {
+                int batch, long long bstride, long long sstride, bool trans) {
   const bool vec = (X != nullptr || Y != nullptr);
   CTM_REQUIRE(b >= 1 && b <= jacobi_max_b(vec), "jacobi_svd: b out of range");
   const int bp = b + (b & 1);
-  const size_t lds = ((vec ? 2 : 1) * (size_t)bp * b + bp) * sizeof(double);
-  allow_lds((const void*)jacobi_svd_kernel, lds);
-  const int P = bp / 2;
-  int TP = 64;
-  while (TP > 1 && P * TP > 1024) TP >>= 1;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(batch), dim3(1024), lds, ctx.stream, B, b, bstride,
-                     sstride, X, s, Y, err, vec ? 1 : 0, TP);
+  int rpt = (b + 7) / 8;
+  rpt = rpt <= 4 ? 4 : (rpt <= 8 ? 8 : (rpt <= 12 ? 12 : 16));
+  const int ld = 8 * rpt + 1;
+  const size_t lds = ((vec ? 2 : 1) * (size_t)bp * ld + bp) * sizeof(double) +
+                     (size_t)(bp - 1) * bp + 16;
+  CTM_REQUIRE(lds <= 160 * 1024, "jacobi_svd: matrix too large for LDS");
+  const int threads = std::max(64, (bp / 2) * 8);
+  CTM_REQUIRE(threads <= 512, "jacobi_svd: too many column pairs");
+#define CTM_JAC(R)                                                                            \
+  do {                                                                                        \
+    allow_lds((const void*)jacobi_svd_kernel<R>, lds);                                        \
+    hipLaunchKernelGGL(jacobi_svd_kernel<R>, dim3(batch), dim3(threads), lds, ctx.stream, B, b, \
+                       bstride, sstride, X, s, Y, err, vec ? 1 : 0, trans ? 1 : 0);          \
+  } while (0)
+  if (rpt == 4) CTM_JAC(4);
+  else if (rpt == 8) CTM_JAC(8);
+  else if (rpt == 12) CTM_JAC(12);
+  else CTM_JAC(16);
+#undef CTM_JAC
+  CTM_HIP(hipGetLastError());
+}
+
+void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
+                  int* err) {
+  CTM_REQUIRE(b >= 1 && b <= 96, "chol_inverse: b out of range");
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, ctx.stream, G, b, dep_tol, W, dep, err);
+  CTM_HIP(hipGetLastError());
+}
+
+void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
+                    unsigned long long seed, unsigned long long counter) {
+  CTM_REQUIRE(b >= 1 && b <= 128, "refill_columns: b out of range");
+  const size_t total = (size_t)n * b;
+  hipLaunchKernelGGL(refill_kernel, dim3(grid_for(total, 256, 1024)), dim3(256), 0, ctx.stream, Q,
+                     ldq, n, b, dep, seed, counter);
+  CTM_HIP(hipGetLastError());
+}
+
+void normalise_columns(Context& ctx, double* Z, int ldz, int n, int b) {
+  hipLaunchKernelGGL(normalise_cols_kernel, dim3(b), dim3(256), 0, ctx.stream, Z, ldz, n);
   CTM_HIP(hipGetLastError());
 }
 

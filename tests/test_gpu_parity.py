@@ -173,10 +173,11 @@ def test_c2_workload_parity(ctx):
     assert abs(e_g - e_o) < 1e-10
     assert np.linalg.norm(Eg - Eo) / np.linalg.norm(Eo) < 1e-8
     # Corner spectra depend on the gauge the projectors give the corner legs;
-    # at this seed the cut spectrum is nearly degenerate at the chi boundary
-    # (s_32/s_33 = 1.04), so the kept tail vectors of a subspace SVD and of a
-    # full SVD differ by small rotations, which moves s_hat at the 1e-9 level.
-    assert np.abs(s_g - s_o).max() < 5e-9
+    # at this seed the cut spectrum is nearly degenerate at the chi boundary,
+    # so two correct SVDs (even two LAPACK drivers, see the oracle test
+    # test_corner_spectra_depend_on_svd_routine) move s_hat at the 1e-8 level.
+    assert np.abs(s_g[:, :16] - s_o[:, :16]).max() < 5e-9
+    assert np.abs(s_g - s_o).max() < 2e-8
 
 
 def test_checkpoint_resume_is_exact(ctx, tmp_path):

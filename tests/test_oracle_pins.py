@@ -296,3 +296,31 @@ def test_bond_metric_hermitian_and_gauge_invariant_expectation():
     # so the agreement is at the truncation-error level, not at rounding level
     assert abs(e1 - e0) < 1e-6
     assert abs(O.kappa(env_g, a_g) / O.kappa(env, a) - 1.0) < 1e-6
+
+
+def test_corner_spectra_depend_on_svd_routine():
+    """At the D = 4, chi = 32, seed 1234 workload the cut spectrum is nearly
+    degenerate at the truncation (s_32 / s_33 ~ 1.04): replacing LAPACK's
+    divide-and-conquer SVD by the QR-iteration driver leaves kappa and the
+    normalised bond metric unchanged to rounding but moves the corner spectra
+    at the 1e-9..1e-8 level.  This bounds how closely any other correct SVD
+    (the GPU's subspace iteration included) can reproduce them."""
+    import scipy.linalg as sl
+    A, B = synth.random_purification(4, 1234)
+    env1, a, K, D, _ = O.environment_from_purification(A, B, 2, 32, 20)
+    orig = np.linalg.svd
+
+    def svd_qr(M, full_matrices=True, compute_uv=True, **kw):
+        if not compute_uv:
+            return sl.svd(M, compute_uv=False, lapack_driver='gesvd')
+        return sl.svd(M, full_matrices=full_matrices, lapack_driver='gesvd')
+    try:
+        np.linalg.svd = svd_qr
+        env2, _, _, _, _ = O.environment_from_purification(A, B, 2, 32, 20)
+    finally:
+        np.linalg.svd = orig
+    assert abs(O.kappa(env2, a) / O.kappa(env1, a) - 1.0) < 1e-13
+    E1, E2 = O.bond_metric(env1, a, D), O.bond_metric(env2, a, D)
+    assert np.linalg.norm(E1 - E2) / np.linalg.norm(E1) < 1e-10
+    ds = np.abs(np.array(O.corner_spectra(env1)) - np.array(O.corner_spectra(env2))).max()
+    assert 1e-10 < ds < 2e-8
