@@ -175,7 +175,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": "dgemm_kernel<128,128,16,2,2> (n x n x n, n=2592)",
+                     "kernel": "dgemm_rr<96,96,16,2,2,0> (n x n x n, n=%d)" % n,
                      "launches": c0, "avg_launch_ms": round(avg_ms, 4)},
         "fu_metric_ms": round(fu_ms, 3),
         "kappa": kappa,

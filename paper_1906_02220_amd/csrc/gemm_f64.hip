@@ -16,11 +16,148 @@
 // Split-K: for skinny outputs the K range is cut into `ksplit` chunks; each
 // chunk writes its partial tile to a workspace and a second kernel sums the
 // chunks in a fixed order (deterministic) and applies alpha and beta.
+//
+// Large products of two row-major operands (the half-system products, the
+// cut matrix and the site-tensor absorption) take a separate kernel,
+// dgemm_rr: 16-byte global loads, A staged [m][k] and B [k][n] in LDS, and a
+// 96 x 96 tile with 2 x 2 waves, so three workgroups share a CU (53 KB LDS
+// each) and an n = 2592 product (27 x 27 tiles) runs as one pass over the
+// 256 CUs.  Its template tag only separates the cut-matrix products from
+// the other users in kernel traces.
 #include "internal.hpp"
+
+#include <cstdint>
 
 namespace ctm {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// C = A B with A (row stride lda) and B (row stride ldb) both
+// contiguous along their second index, lda and ldb even and both base
+// pointers 16-byte aligned (checked by the dispatcher).  blockIdx.x is the
+// tile (row-major over the tile grid), blockIdx.y the batch.
+// Offsets within one matrix are 32-bit (the dispatcher checks that they
+// fit), which keeps the address arithmetic of the loads short.
+//
+// Split-K: blockIdx.z selects the K chunk [z kchunk, (z + 1) kchunk); with
+// ksplit > 1 the chunk's partial product goes to W (row stride N, one M x N
+// slab per (batch, chunk)) for the fixed-order reduction.
+template <int BM, int BN, int BK, int WGM, int WGN, int TAG>
+__global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
+    int M, int N, int K, const double* __restrict__ A, int lda, long long abs_,
+    const double* __restrict__ B, int ldb, long long bbs, double* __restrict__ C, int ldc,
+    long long cbs, int ksplit, int kchunk, double* __restrict__ W) {
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  constexpr int SA = BK + 2, SB = BN + 2;
+  constexpr int AV = BM * BK / 2 / NT;  // 16-byte loads of A per thread per K tile
+  constexpr int BV = BK * BN / 2 / NT;
+  static_assert(AV >= 1 && BV >= 1 && (BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0,
+                "tile does not split evenly into 16-byte loads");
+  static_assert(TI * 16 == WM && TJ * 16 == WN, "wave tile must be a multiple of 16");
+  __shared__ double As[2][BM * SA];
+  __shared__ double Bs[2][BK * SB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
+  const int ntn = (N + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  A += blockIdx.y * abs_;
+  B += blockIdx.y * bbs;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  if (ksplit > 1) {
+    C = W + ((long long)blockIdx.y * ksplit + blockIdx.z) * ((long long)M * N);
+    ldc = N;
+  } else {
+    C += blockIdx.y * cbs;
+  }
+  const bool full_m = (m0 + BM <= M), full_n = (n0 + BN <= N);
+
+  d2v ra[AV], rb[BV];
+  auto load = [&](int kt) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int p = tid + e * NT;
+      const int r = p / (BK / 2), k = (p % (BK / 2)) * 2;
+      const int gm = m0 + r, gk = kt + k;
+      if ((full_m || gm < M) && gk + 1 < kend) {
+        ra[e] = *(const d2v*)(A + gm * lda + gk);
+      } else {
+        ra[e].x = (gm < M && gk < kend) ? A[gm * lda + gk] : 0.0;
+        ra[e].y = (gm < M && gk + 1 < kend) ? A[gm * lda + gk + 1] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int p = tid + e * NT;
+      const int k = p / (BN / 2), c = (p % (BN / 2)) * 2;
+      const int gk = kt + k, gn = n0 + c;
+      if (gk < kend && (full_n || gn + 1 < N)) {
+        rb[e] = *(const d2v*)(B + gk * ldb + gn);
+      } else {
+        rb[e].x = (gk < kend && gn < N) ? B[gk * ldb + gn] : 0.0;
+        rb[e].y = (gk < kend && gn + 1 < N) ? B[gk * ldb + gn + 1] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int p = tid + e * NT;
+      *(d2v*)(&As[buf][(p / (BK / 2)) * SA + (p % (BK / 2)) * 2]) = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int p = tid + e * NT;
+      *(d2v*)(&Bs[buf][(p / (BN / 2)) * SB + (p % (BN / 2)) * 2]) = rb[e];
+    }
+  };
+
+  d4v acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+  const int lr = lane & 15, lk = lane >> 4;
+  load(kbeg);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = kbeg; kt < kend; kt += BK) {
+    const bool more = kt + BK < kend;
+    if (more) load(kt + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) av[i] = As[buf][(wm + i * 16 + lr) * SA + kk + lk];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bv[j] = Bs[buf][(kk + lk) * SB + wn + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // Plain store of the accumulators: an alpha / beta epilogue here costs
+  // enough registers to drop the occupancy to two workgroups per CU, so the
+  // dispatcher sends only C = A B products to this kernel.
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * r + lk, gn = n0 + wn + j * 16 + lr;
+        if (gm < M && gn < N) C[gm * ldc + gn] = acc[i][j][r];
+      }
+}
 
 template <int BM, int BN, int BK, int WGM, int WGN, bool A_KC, bool B_NC>
 __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_kernel(
@@ -248,6 +385,59 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
     hipLaunchKernelGGL(scale_matrix_kernel, dim3(blocks), dim3(256), 0, ctx.stream, M, N, batch,
                        beta, C.p, C.rs, C.cs, C.bs);
     CTM_HIP(hipGetLastError());
+    return;
+  }
+  // Large products of two row-major operands with 16-byte aligned rows.
+  auto aligned = [](const void* p, long long ld) {
+    return ((reinterpret_cast<uintptr_t>(p) & 15) == 0) && (ld % 2 == 0);
+  };
+  const long long i32 = 0x7fffffffLL;
+  const bool fits32 = (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
+                      (long long)M * C.rs + N < i32;
+  if (alpha == 1.0 && beta == 0.0 && A.cs == 1 && B.cs == 1 && C.cs == 1 &&
+      aligned(A.p, A.rs) && aligned(B.p, B.rs) && (A.bs % 2 == 0) && (B.bs % 2 == 0) && fits32 &&
+      M >= 384 && N >= 384 && K >= 16) {
+    constexpr int BM = 96, BN = 96, BK = 16;
+    const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+    CTM_REQUIRE(tiles <= i32 && batch <= 65535, "gemm: grid too large");
+    // three workgroups fit on a CU; split K when the tiles fill less than
+    // one pass and every chunk keeps at least 32 K tiles
+    const long long slots = 3LL * ctx.num_cus;
+    int ksplit = 1;
+    if (tiles < slots && K >= 64 * BK) {
+      ksplit = (int)std::min<long long>(slots / tiles, K / (32 * BK));
+      ksplit = std::max(1, std::min(ksplit, 16));
+    }
+    int kchunk = K;
+    double* W = nullptr;
+    if (ksplit > 1) {
+      kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
+      ksplit = (K + kchunk - 1) / kchunk;
+    }
+    if (ksplit > 1) {
+      const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
+      if (ctx.splitk_ws.bytes < need) {
+        CTM_HIP(hipStreamSynchronize(ctx.stream));
+        ctx.splitk_ws.alloc(need);
+      }
+      W = ctx.splitk_ws.d();
+    }
+    const dim3 grid((unsigned)(tiles / batch), batch, ksplit), block(256);
+    const int lda = (int)A.rs, ldb = (int)B.rs, ldc = (int)C.rs;
+    if (cls == 0)
+      hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, 0>), grid, block, 0, ctx.stream, M, N, K,
+                         A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W);
+    else
+      hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, 1>), grid, block, 0, ctx.stream, M, N, K,
+                         A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W);
+    CTM_HIP(hipGetLastError());
+    if (ksplit > 1) {
+      const long long total = (long long)M * N * batch;
+      const int blocks = (int)std::min<long long>((total + 255) / 256, 8192);
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, ctx.stream, M, N,
+                         ksplit, batch, 1.0, W, 0.0, C.p, C.rs, C.cs, C.bs);
+      CTM_HIP(hipGetLastError());
+    }
     return;
   }
   // Contiguity of the operands decides the load mapping (correct either way).

@@ -394,9 +394,16 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
         // rotation parameters, computed unconditionally (c = 1, s = 0 when idle)
         const double g2 = rot ? 2.0 * ga : 1.0;
         const double zeta = rot ? (be - al) * rcp_nr(g2) : 0.0;
-        const double az = fmin(fabs(zeta), 1e150);
-        const double w = fma(az, az, 1.0);
-        double tt = rcp_nr(az + w * rsq_nr(w));   // 1 / (|zeta| + sqrt(1 + zeta^2))
+        // t = 1 / (|zeta| + sqrt(1 + zeta^2)); above 1e150 zeta^2 would
+        // overflow and t = 1 / (2 |zeta|) is exact to rounding.  The angle must
+        // not be clamped: a too large angle on a strongly graded pair
+        // overshoots and the pair never settles.  An infinite zeta gives t = 0
+        // (no rotation, and the pair does not count as changed).
+        const double az = fabs(zeta);
+        const double azc = fmin(az, 1e150);
+        const double w = fma(azc, azc, 1.0);
+        const double den = (az < 1e150) ? azc + w * rsq_nr(w) : 2.0 * az;
+        double tt = (den < INFINITY) ? rcp_nr(den) : 0.0;
         tt = rot ? (zeta < 0.0 ? -tt : tt) : 0.0;
         if (tt != 0.0) {
           const double c = rsq_nr(fma(tt, tt, 1.0));
