@@ -77,6 +77,48 @@ def cpu_baseline(D, chi, seed, moves=2):
                                                                     chi * D * D, dt)}
 
 
+COPY_BYTES = 512 << 20
+
+
+def calibrate_copy(torch):
+    """Three plain device-to-device copies of COPY_BYTES each: the kernel the
+    HBM byte counters are scaled against."""
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1906_02220_amd", "csrc", "gemm_f64.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(path):
+    """HBM bytes per launch of the n^3 GEMM from the counter summary (lines
+    'key: value'); None when the summary is missing or was taken on another
+    version of the GEMM source."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("gemm_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +129,10 @@ def main():
     ap.add_argument("--chi", type=int, default=72)
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_gemm_f64_D6_chi72.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_dgemm_rr_cut_D6_chi72.txt"),
+                    help="HBM-counter summary of the n^3 GEMM (bytes per launch)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -95,6 +140,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     from paper_1906_02220_amd import ctm, synth
 
     D, chi, seed = args.D, args.chi, args.seed
@@ -132,13 +180,7 @@ def main():
     per_launch = 2.0 * float(n) ** 3
     avg_ms = ms0 / max(c0, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            with open(args.traffic_json) as f:
-                traffic = json.load(f).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = read_traffic(args.traffic)
 
     # a9: bond metric, norm and one expectation value on the converged environment
     H = synth.bond_operator_real(synth.random_coefficients(6))
