@@ -110,7 +110,7 @@ ctm::EnvOptions to_options(const ctm_opts* o, int d) {
 void check_precision(int p) {
   if (p != CTM_PREC_F64 && p != CTM_PREC_F32 && !(p >= CTM_PREC_BF16X3 && p <= CTM_PREC_BF16X6))
     throw ctm::Error(CTM_EINVAL, "unknown precision mode");
-  if (p != CTM_PREC_F64) throw ctm::Error(CTM_EINVAL, "precision mode not available in this build");
+  if (!ctm::mixed_mode_supported(p)) throw ctm::Error(CTM_EINVAL, "precision mode not available");
 }
 
 }  // namespace

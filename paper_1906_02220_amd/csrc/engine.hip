@@ -197,8 +197,8 @@ void Env::corner(int f) {
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t1.d(), t2.d(), 4, d4, p0321);  // [de,ga,u,l]
   // t1 = t2 a_f : [(de,ga),(u,l)] x [(u,l),(dd,r)]
-  gemm_f64(ctx, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d), rowmajor(arot[f].d(), d * d),
-           0.0, out_rowmajor(t1.d(), d * d));
+  gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
+             rowmajor(arot[f].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));
   const long long e4[4] = {chi, chi, d, d};
   const int p0213[4] = {0, 2, 1, 3};
   permute(ctx, t1.d(), Qb[f].d(), 4, e4, p0213);  // [de,dd,ga,r]
@@ -280,12 +280,12 @@ void Env::move(int k) {
     if (!qvalid[(k + r) & 3]) corner(k + r);
   const int q0 = k, q1 = (k + 1) & 3, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
   // a5: halves and the cut matrix
-  gemm_f64(ctx, n, n, n, 1.0, rowmajor(Qb[q0].d(), n), rowmajor(Qb[q1].d(), n), 0.0,
-           out_rowmajor(U.d(), n), 1, 0);
-  gemm_f64(ctx, n, n, n, 1.0, rowmajor(Qb[q2].d(), n), rowmajor(Qb[q3].d(), n), 0.0,
-           out_rowmajor(Lt.d(), n), 1, 0);
-  gemm_f64(ctx, n, n, n, 1.0, rowmajor(Lt.d(), n), rowmajor(U.d(), n), 0.0,
-           out_rowmajor(Mt.d(), n), 1, 0);
+  gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Qb[q0].d(), n), rowmajor(Qb[q1].d(), n),
+             0.0, out_rowmajor(U.d(), n), 1, 0);
+  gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Qb[q2].d(), n), rowmajor(Qb[q3].d(), n),
+             0.0, out_rowmajor(Lt.d(), n), 1, 0);
+  gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Lt.d(), n), rowmajor(U.d(), n), 0.0,
+             out_rowmajor(Mt.d(), n), 1, 0);
   // a6: projectors
   svd_top(Mt.d(), k);
   const int kk = std::min(chi, b);
@@ -313,8 +313,8 @@ void Env::move(int k) {
   const long long d4[4] = {chi, d, d, chi};
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t1.d(), t2.d(), 4, d4, p0321);  // [de,k2,u,l]
-  gemm_f64(ctx, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d), rowmajor(arot[q0].d(), d * d),
-           0.0, out_rowmajor(t1.d(), d * d));  // [de,k2,dd,r]
+  gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
+             rowmajor(arot[q0].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));  // [de,k2,dd,r]
   const long long e4[4] = {chi, chi, d, d};
   const int p0213[4] = {0, 2, 1, 3};
   permute(ctx, t1.d(), t2.d(), 4, e4, p0213);  // [de,dd,k2,r]
@@ -389,8 +389,8 @@ void Env::ring() {
            out_rowmajor(t1.d(), dc));                               // [h,x][l,a]
   const int p3012[4] = {3, 0, 1, 2};
   permute(ctx, t1.d(), Lt.d(), 4, d4, p3012);                       // [a,h,x,l]
-  gemm_f64(ctx, d * d, d * d, chi * chi, 1.0, rowmajor(U.d(), chi * chi), rowmajor(Lt.d(), d * d), 0.0,
-           out_rowmajor(t2.d(), d * d));                            // [u,r][x,l]
+  gemm_mixed(ctx, opt.precision, d * d, d * d, chi * chi, 1.0, rowmajor(U.d(), chi * chi),
+             rowmajor(Lt.d(), d * d), 0.0, out_rowmajor(t2.d(), d * d));  // [u,r][x,l]
   const long long f4[4] = {d, d, d, d};
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t2.d(), E.d(), 4, f4, p0321);                        // [u,l,x,r]

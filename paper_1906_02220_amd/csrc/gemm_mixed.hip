@@ -1,0 +1,500 @@
+// Reduced-precision contractions with FP64 inputs and outputs.
+//
+// CTM_PREC_F32: one FP32 product.  Operands are rounded to FP32 while they
+// are staged into LDS, v_mfma_f32_16x16x4_f32 accumulates in FP32, and the
+// FP32 result is widened to FP64.
+//
+// CTM_PREC_BF16X3 / X4: split-precision products on the BF16 matrix cores.
+// Every row of A (and every column of B) is scaled by a power of two 2^-e
+// with e chosen so that the row's largest entry falls below 1 in magnitude,
+// then cut into S slices of 8 bits each:
+//     y = x 2^(8 - e),  q_0 = rint(y),  q_i = rint(256 (y_(i-1) - q_(i-1))),
+// stored as the BF16 numbers q_i 2^(-8 i) (|q_0| <= 256, |q_i| <= 128 for
+// i >= 1, so every slice is exact in BF16's 8-bit significand).  Then
+//     A B = 2^(eA + eB - 16) sum_{i + j < S} A_i B_j
+// up to the dropped levels i + j >= S and the residual of the S-th slice,
+// both about 2^(-8 S) relative to the row and column scales.
+//
+// The products run on v_mfma_f32_16x16x32_bf16 with FP32 accumulation over
+// K chunks of 128:
+//   * level 0 (A_0 B_0) has its own accumulator: products are integers below
+//     2^16 in magnitude and a chunk sum stays below 2^23, so the FP32 sum is
+//     exact;
+//   * all other pairs share a second accumulator, whose FP32 rounding is at
+//     most about 2^-32 relative to the level-0 scale.
+// After every chunk both accumulators are added into an FP64 accumulator
+// held in registers, and the epilogue applies the row and column scales
+// exactly (ldexp).
+//
+// The slices are built by two memory-bound kernels (a max-abs reduction and
+// the split itself), stored K-contiguous for both operands so that a lane
+// reads the 8 consecutive k values an MFMA operand needs as one 16-byte LDS
+// read.
+//
+// MFMA operand fragments (checked on the device with an in-bounds probe):
+//   16x16x32 BF16: lane l holds A[l % 16][8 (l / 16) + e] and
+//                  B[8 (l / 16) + e][l % 16], e < 8;
+//   16x16x4 F32:   lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+//   accumulator register r of lane l holds C[4 (l / 16) + r][l % 16] (unlike
+//   the FP64 MFMA, whose register r holds row 4 r + l / 16).
+#include <climits>
+#include <cmath>
+#include <cstdint>
+
+#include "ctm.h"
+#include "internal.hpp"
+
+namespace ctm {
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 128;  // K chunk of exact FP32 accumulation (BF16 path)
+
+// ------------------------------------------------------------ slicing
+
+// max |x| over each row r of the R x K view (element (r, k) at p[r rs + k]),
+// one workgroup per row.
+__global__ __launch_bounds__(256) void rowmax_contig_kernel(const double* __restrict__ p,
+                                                            long long rs, int K,
+                                                            double* __restrict__ mx) {
+  __shared__ double sh[256];
+  const int r = blockIdx.x;
+  const double* row = p + r * rs;
+  double m = 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const double v = fabs(row[k]);
+    m = (v > m || v != v) ? v : m;  // a NaN wins
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = sh[threadIdx.x + s];
+      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mx[r] = sh[0];
+}
+
+// max |x| over each column n of a K x N row-major matrix (row stride ld):
+// thread = column, blockIdx.y = K slab, combined with an integer atomic max
+// on the bit pattern (non-negative doubles order like their bits; a NaN's
+// pattern is above every finite one).  mx must start at +0.
+__global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ p, long long ld,
+                                                     int K, int N, int kslab,
+                                                     unsigned long long* __restrict__ mx) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int k0 = blockIdx.y * kslab, k1 = min(K, k0 + kslab);
+  double m = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double v = fabs(p[k * ld + n]);
+    m = (v > m || v != v) ? v : m;
+  }
+  atomicMax(mx + n, (unsigned long long)__double_as_longlong(m));
+}
+
+__device__ inline int scale_exponent(double m) {
+  // smallest e with m < 2^e (0 for an all-zero or non-finite row)
+  if (!(m > 0.0) || !(m < INFINITY)) return 0;
+  return ilogb(m) + 1;
+}
+
+// Cut one value into S slices (see the file comment); a non-finite value
+// gives a NaN first slice so that the product row turns NaN.
+template <int S>
+__device__ inline void cut(double x, int e, __bf16* out) {
+  if (!isfinite(x)) {
+    out[0] = (__bf16)NAN;
+#pragma unroll
+    for (int i = 1; i < S; ++i) out[i] = (__bf16)0.0f;
+    return;
+  }
+  double y = ldexp(x, 8 - e);
+  double w = 1.0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const double q = rint(y);
+    out[i] = (__bf16)(float)(q * w);
+    y = (y - q) * 256.0;
+    w *= 1.0 / 256.0;
+  }
+}
+
+// Slices of the R x K view (element (r, k) at p[r rs + k cs]) into
+// Q[i][r][k], row pitch Kp (zero for K <= k < Kp).  A 64 x 64 tile per
+// workgroup goes through LDS so that the global reads are coalesced along
+// whichever index is contiguous and the slice writes along k.
+template <int S>
+__global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p, long long rs,
+                                                    long long cs, int R, int K, int Kp,
+                                                    const double* __restrict__ mx,
+                                                    __bf16* __restrict__ Q) {
+  __shared__ double tile[64][65];
+  const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  if (cs == 1) {
+    // rows contiguous along k: consecutive threads walk k
+    for (int idx = t; idx < 64 * 64; idx += 256) {
+      const int rr = idx >> 6, kk = idx & 63;
+      const int r = r0 + rr, k = k0 + kk;
+      tile[rr][kk] = (r < R && k < K) ? p[r * rs + k] : 0.0;
+    }
+  } else {
+    // contiguous along r: consecutive threads walk r
+    for (int idx = t; idx < 64 * 64; idx += 256) {
+      const int kk = idx >> 6, rr = idx & 63;
+      const int r = r0 + rr, k = k0 + kk;
+      tile[rr][kk] = (r < R && k < K) ? p[r * rs + k * cs] : 0.0;
+    }
+  }
+  __syncthreads();
+  // each thread: one row, 16 consecutive k (two 8-value groups)
+  const int rr = t >> 2, kq = (t & 3) * 16;
+  const int r = r0 + rr;
+  if (r >= R) return;
+  const int e = scale_exponent(mx[r]);
+  const long long slab = (long long)R * Kp;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int kb = k0 + kq + 8 * g;
+    if (kb >= Kp) break;
+    __bf16 v[S][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      __bf16 o[S];
+      cut<S>(tile[rr][kq + 8 * g + u], e, o);
+#pragma unroll
+      for (int i = 0; i < S; ++i) v[i][u] = o[i];
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      bf8 w;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) w[u] = v[i][u];
+      *(bf8*)(Q + i * slab + (long long)r * Kp + kb) = w;
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ BF16 slice GEMM
+
+// C (M x N, row stride ldc, FP64) = A B from the slices Aq[S][M][Kp] and
+// Bq[S][N][Kp] (B stored transposed) and the row / column maxima.  128 x 128
+// tile, 8 waves as 4 x 2, each wave 32 x 64 (2 x 4 MFMA tiles); K steps of
+// 32 through double-buffered LDS with a register prefetch of the next step.
+template <int S, int TAG>
+__global__ __launch_bounds__(512) void gemm_bf16s_kernel(
+    int M, int N, int Kp, const __bf16* __restrict__ Aq, const __bf16* __restrict__ Bq,
+    const double* __restrict__ amax, const double* __restrict__ bmax, double* __restrict__ C,
+    int ldc) {
+  constexpr int BM = 128, BN = 128, BK = 32, PITCH = BK + 8;  // bf16 units; 80-byte rows
+  constexpr int TI = 2, TJ = 4;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][S][BM * PITCH];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][BN * PITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  const int ntn = (N + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  const long long aslab = (long long)M * Kp, bslab = (long long)N * Kp;
+  // global -> register mapping: thread t loads 16 bytes (8 k) of row t / 4
+  const int lrow = tid >> 2, lk = (tid & 3) * 8;
+  const bool arow_ok = (m0 + lrow) < M, brow_ok = (n0 + lrow) < N;
+  const __bf16* ag = Aq + (long long)(m0 + lrow) * Kp + lk;
+  const __bf16* bg = Bq + (long long)(n0 + lrow) * Kp + lk;
+  u4 ra[S], rb[S];
+  auto load = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      ra[i] = arow_ok ? *(const u4*)(ag + i * aslab + kt) : u4{0, 0, 0, 0};
+      rb[i] = brow_ok ? *(const u4*)(bg + i * bslab + kt) : u4{0, 0, 0, 0};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      *(u4*)(&As[buf][i][lrow * PITCH + lk]) = ra[i];
+      *(u4*)(&Bs[buf][i][lrow * PITCH + lk]) = rb[i];
+    }
+  };
+  f4 acc0[TI][TJ], accr[TI][TJ];
+  double acc[TI][TJ][4];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      acc0[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      accr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+    }
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[i][j][r] += (double)acc0[i][j][r] + (double)accr[i][j][r];
+        acc0[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        accr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < Kp; kt += BK) {
+    const bool more = kt + BK < Kp;
+    if (more) load(kt + BK);
+    bf8 a[TI][S];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        a[i][s] = *(const bf8*)(&As[buf][s][(wm + 16 * i + fr) * PITCH + fk]);
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      bf8 b[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) b[s] = *(const bf8*)(&Bs[buf][s][(wn + 16 * j + fr) * PITCH + fk]);
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[0], acc0[i][j], 0, 0, 0);
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+          for (int q = 0; q < S; ++q)
+            if (p + q >= 1 && p + q < S)
+              accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][p], b[q], accr[i][j], 0, 0, 0);
+      }
+    }
+    if (((kt + BK) % kChunk) == 0 || !more) flush();
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // epilogue: C = acc 2^(eA + eB - 16)
+  const int lq = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm + 16 * i + 4 * lq + r;
+      if (gm >= M) continue;
+      const int ea = scale_exponent(amax[gm]);
+      const bool abad = !(amax[gm] < INFINITY);
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int gn = n0 + wn + 16 * j + fr;
+        if (gn < N) {
+          const double bm = bmax[gn];
+          const double v = ldexp(acc[i][j][r], ea + scale_exponent(bm) - 16);
+          C[(long long)gm * ldc + gn] = (abad || !(bm < INFINITY)) ? NAN : v;
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------ FP32 GEMM
+
+// C = A B with FP64 operands rounded to FP32 on the way into LDS, FP32 MFMA
+// and FP32 accumulation; same staging as the FP64 row-major kernel (96 x 96
+// tile, 2 x 2 waves, 16-byte global loads, double-buffered LDS).
+template <int TAG>
+__global__ __launch_bounds__(256) void gemm_f32x1_kernel(int M, int N, int K,
+                                                         const double* __restrict__ A, int lda,
+                                                         const double* __restrict__ B, int ldb,
+                                                         double* __restrict__ C, int ldc) {
+  constexpr int BM = 96, BN = 96, BK = 16, NT = 256;
+  constexpr int WM = 48, WN = 48, TI = 3, TJ = 3;
+  constexpr int SA = BK + 1, SB = BN + 1;
+  constexpr int AV = BM * BK / 2 / NT, BV = BK * BN / 2 / NT;
+  __shared__ float As[2][BM * SA];
+  __shared__ float Bs[2][BK * SB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int ntn = (N + BN - 1) / BN;
+  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  const bool full_m = (m0 + BM <= M), full_n = (n0 + BN <= N);
+  d2v ra[AV], rb[BV];
+  auto load = [&](int kt) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int p = tid + e * NT;
+      const int r = p / (BK / 2), k = (p % (BK / 2)) * 2;
+      const int gm = m0 + r, gk = kt + k;
+      if ((full_m || gm < M) && gk + 1 < K) {
+        ra[e] = *(const d2v*)(A + gm * lda + gk);
+      } else {
+        ra[e].x = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
+        ra[e].y = (gm < M && gk + 1 < K) ? A[gm * lda + gk + 1] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int p = tid + e * NT;
+      const int k = p / (BN / 2), c = (p % (BN / 2)) * 2;
+      const int gk = kt + k, gn = n0 + c;
+      if (gk < K && (full_n || gn + 1 < N)) {
+        rb[e] = *(const d2v*)(B + gk * ldb + gn);
+      } else {
+        rb[e].x = (gk < K && gn < N) ? B[gk * ldb + gn] : 0.0;
+        rb[e].y = (gk < K && gn + 1 < N) ? B[gk * ldb + gn + 1] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AV; ++e) {
+      const int p = tid + e * NT;
+      float* d = &As[buf][(p / (BK / 2)) * SA + (p % (BK / 2)) * 2];
+      d[0] = (float)ra[e].x;
+      d[1] = (float)ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < BV; ++e) {
+      const int p = tid + e * NT;
+      float* d = &Bs[buf][(p / (BN / 2)) * SB + (p % (BN / 2)) * 2];
+      d[0] = (float)rb[e].x;
+      d[1] = (float)rb[e].y;
+    }
+  };
+  f4 acc[TI][TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int lr = lane & 15, lk = lane >> 4;
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < K; kt += BK) {
+    const bool more = kt + BK < K;
+    if (more) load(kt + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float av[TI], bv[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) av[i] = As[buf][(wm + i * 16 + lr) * SA + kk + lk];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bv[j] = Bs[buf][(kk + lk) * SB + wn + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * lk + r, gn = n0 + wn + j * 16 + lr;
+        if (gm < M && gn < N) C[gm * ldc + gn] = (double)acc[i][j][r];
+      }
+}
+
+namespace {
+
+template <int S>
+void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda,
+               const double* B, long long ldb, double* C, long long ldc, int cls) {
+  const int tag = cls == 0 ? 0 : 1;
+  const int Kp = (K + 31) / 32 * 32;
+  const size_t aq = (size_t)S * M * Kp, bq = (size_t)S * N * Kp;
+  const size_t need = (aq + bq) * sizeof(__bf16) + (size_t)(M + N) * sizeof(double) + 256;
+  if (ctx.mixed_ws.bytes < need) {
+    CTM_HIP(hipStreamSynchronize(ctx.stream));
+    ctx.mixed_ws.alloc(need);
+  }
+  char* base = (char*)ctx.mixed_ws.p;
+  __bf16* Aq = (__bf16*)base;
+  __bf16* Bq = Aq + aq;
+  double* amax = (double*)(((uintptr_t)(Bq + bq) + 255) & ~(uintptr_t)255);
+  double* bmax = amax + M;
+  // maxima: rows of A (contiguous), columns of B (atomic max over K slabs)
+  hipLaunchKernelGGL(rowmax_contig_kernel, dim3(M), dim3(256), 0, ctx.stream, A, lda, K, amax);
+  fill_zero(ctx, bmax, (size_t)N);
+  const int kslab = 64;
+  hipLaunchKernelGGL(colmax_kernel, dim3((N + 255) / 256, (K + kslab - 1) / kslab), dim3(256), 0,
+                     ctx.stream, B, ldb, K, N, kslab, (unsigned long long*)bmax);
+  CTM_HIP(hipGetLastError());
+  // slices: A as [M][Kp] (rows contiguous), B^T as [N][Kp] (columns of B)
+  hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (M + 63) / 64),
+                     dim3(256), 0, ctx.stream, A, lda, 1LL, M, K, Kp, amax, Aq);
+  hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (N + 63) / 64),
+                     dim3(256), 0, ctx.stream, B, 1LL, ldb, N, K, Kp, bmax, Bq);
+  CTM_HIP(hipGetLastError());
+  const long long tiles = (long long)((M + 127) / 128) * ((N + 127) / 128);
+  CTM_REQUIRE(tiles <= INT_MAX, "gemm_mixed: grid too large");
+  // timing class 0 covers the slice product only (the slicing is class 1)
+  ScopedTimer t0(ctx, cls == 0 ? 0 : -1, 2.0 * M * N * (double)K);
+  if (tag == 0)
+    hipLaunchKernelGGL((gemm_bf16s_kernel<S, 0>), dim3((unsigned)tiles), dim3(512), 0, ctx.stream,
+                       M, N, Kp, Aq, Bq, amax, bmax, C, (int)ldc);
+  else
+    hipLaunchKernelGGL((gemm_bf16s_kernel<S, 1>), dim3((unsigned)tiles), dim3(512), 0, ctx.stream,
+                       M, N, Kp, Aq, Bq, amax, bmax, C, (int)ldc);
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+bool mixed_mode_supported(int mode) {
+  return mode == CTM_PREC_F64 || mode == CTM_PREC_F32 || mode == CTM_PREC_BF16X3 ||
+         mode == CTM_PREC_BF16X4;
+}
+
+void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View A, View B,
+                double beta, ViewOut C, int batch, int cls) {
+  CTM_REQUIRE(mixed_mode_supported(mode), "precision mode not available");
+  const long long i32 = INT_MAX;
+  const bool plain = mode != CTM_PREC_F64 && alpha == 1.0 && beta == 0.0 && batch == 1 &&
+                     A.cs == 1 && B.cs == 1 && C.cs == 1 && M >= 1 && N >= 1 && K >= 1 &&
+                     (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
+                     (long long)M * C.rs + N < i32 &&
+                     ((reinterpret_cast<uintptr_t>(A.p) | reinterpret_cast<uintptr_t>(B.p)) & 15) == 0 &&
+                     A.rs % 2 == 0 && B.rs % 2 == 0;
+  if (!plain) {
+    // FP64 for every contraction the reduced-precision kernels do not cover
+    gemm_f64(ctx, M, N, K, alpha, A, B, beta, C, batch, cls);
+    return;
+  }
+  const double flops = 2.0 * M * N * (double)K;
+  ScopedTimer t1(ctx, 1, flops);
+  const int tag = cls == 0 ? 0 : 1;
+  if (mode == CTM_PREC_F32) {
+    ScopedTimer t0(ctx, cls == 0 ? 0 : -1, flops);
+    const long long tiles = (long long)((M + 95) / 96) * ((N + 95) / 96);
+    CTM_REQUIRE(tiles <= i32, "gemm_mixed: grid too large");
+    if (tag == 0)
+      hipLaunchKernelGGL((gemm_f32x1_kernel<0>), dim3((unsigned)tiles), dim3(256), 0, ctx.stream,
+                         M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);
+    else
+      hipLaunchKernelGGL((gemm_f32x1_kernel<1>), dim3((unsigned)tiles), dim3(256), 0, ctx.stream,
+                         M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);
+    CTM_HIP(hipGetLastError());
+  } else if (mode == CTM_PREC_BF16X3) {
+    run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, C.rs, cls);
+  } else {
+    run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, C.rs, cls);
+  }
+}
+
+}  // namespace ctm

@@ -81,6 +81,7 @@ struct Context {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   DevBuf splitk_ws;     // split-K partial products
+  DevBuf mixed_ws;      // operand slices and scales of the reduced-precision GEMMs
   DevBuf scratch_small; // reductions and flags
   Context() = default;
   Context(const Context&) = delete;
@@ -129,10 +130,14 @@ inline ViewOut out_rowmajor(double* p, long long ld, long long bs = 0) { return 
 void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, double beta,
               ViewOut C, int batch = 1, int cls = -1);
 
-// Reduced-precision contractions with FP64 inputs and outputs (precision
-// mode as in ctm.h: 1 = FP32 MFMA, 3..6 = number of BF16 slices).
+// Contraction in the precision mode of ctm.h (CTM_PREC_*) with FP64 inputs
+// and outputs: FP32 MFMA for CTM_PREC_F32, BF16 slices for CTM_PREC_BF16X*.
+// Products the reduced-precision kernels do not cover (alpha != 1, beta != 0,
+// batched or transposed operands) and CTM_PREC_F64 run as gemm_f64.
 void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View A, View B,
                 double beta, ViewOut C, int batch = 1, int cls = -1);
+// Modes gemm_mixed implements.
+bool mixed_mode_supported(int mode);
 
 // out = permutation of `in` (row-major dims[0..rank-1]); out axis a is in
 // axis perm[a].  rank <= 8.

@@ -153,9 +153,9 @@ __global__ void sum_final_kernel(const double* partial, int nb, double* out) {
 
 // ------------------------------------------------------------ Gram-Cholesky
 
-// Cholesky factor and its inverse in one pass, register-tiled: 256 threads as
-// a 16 x 16 grid, thread (ti, tj) owning entries (ti + 16 r, tj + 16 c),
-// r, c < 6, of the symmetric Schur complement S and of X (both 96 x 96,
+// Cholesky factor and its inverse in one pass, register-tiled: TG x TG
+// threads, thread (ti, tj) owning entries (ti + TG r, tj + TG c),
+// r, c < NR = 96 / TG, of the symmetric Schur complement S and of X (both 96 x 96,
 // zero beyond b so that no row or column needs a guard).  Step k eliminates
 // column k below the pivot (S -= s_k s_k^T / piv on the trailing block) and
 // applies the same row operation to X, then scales row k of X by 1/sqrt(piv).
@@ -163,16 +163,19 @@ __global__ void sum_final_kernel(const double* partial, int nb, double* out) {
 // W = D^-1 X^T has Z W orthonormal.  Columns whose pivot falls below dep_tol
 // (numerically dependent) are skipped: no elimination, flag set.  All
 // updates are unconditional FMAs with masked multipliers.
-__global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict__ G, int b,
-                                                       double dep_tol, double* __restrict__ Wout,
-                                                       int* __restrict__ dep, int* err) {
+template <int TG>
+__global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restrict__ G, int b,
+                                                           double dep_tol, double* __restrict__ Wout,
+                                                           int* __restrict__ dep, int* err) {
+  constexpr int NR = 96 / TG;
+  static_assert(NR * TG == 96, "the thread grid must tile 96");
   __shared__ double Dn[96];
-  __shared__ double rowk[96];
-  __shared__ double xrow[96];
+  __shared__ double rowk[2][96];
+  __shared__ double xrow[2][96];
   __shared__ int depl[96];
   __shared__ int bad;
   const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;
+  const int ti = t / TG, tj = t % TG;
   if (t == 0) bad = 0;
   if (t < 96) {
     double dv = 0.0;
@@ -183,12 +186,12 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict_
     Dn[t] = dv;
   }
   __syncthreads();
-  double S[6][6], X[6][6];
+  double S[NR][NR], X[NR][NR];
 #pragma unroll
-  for (int r = 0; r < 6; ++r)
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const int i = ti + 16 * r, j = tj + 16 * c;
+    for (int c = 0; c < NR; ++c) {
+      const int i = ti + TG * r, j = tj + TG * c;
       double v = 0.0;
       if (i < b && j < b) {
         const double g = G[i * b + j];
@@ -199,55 +202,58 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict_
       S[r][c] = v;
       X[r][c] = (i == j) ? 1.0 : 0.0;
     }
-  for (int k = 0; k < b; ++k) {
-    const int rk = k >> 4;
-    if (ti == (k & 15)) {
-      // row k of S and X, selected from the owning register row without
-      // dynamic indexing
+  // The 96 steps are unrolled so that k, and with it the register row
+  // k / TG that holds row k and the blocks the step can touch, are
+  // compile-time constants: no select chains, and register blocks that lie
+  // entirely before the pivot are skipped.  Row k is broadcast through a
+  // double-buffered LDS row, so one barrier per step suffices (a buffer is
+  // rewritten two steps later, after every reader has passed the barrier in
+  // between).
+#pragma unroll 96
+  for (int k = 0; k < 96; ++k) {
+    if (k >= b) continue;                                     // uniform: b is a kernel argument
+    const int rk = k / TG;
+    const int buf = k & 1;
+    if (ti == (k % TG)) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        double sv = S[0][c], xv = X[0][c];
-#pragma unroll
-        for (int r = 1; r < 6; ++r) {
-          sv = (rk == r) ? S[r][c] : sv;
-          xv = (rk == r) ? X[r][c] : xv;
-        }
-        rowk[tj + 16 * c] = sv;
-        xrow[tj + 16 * c] = xv;
+      for (int c = 0; c < NR; ++c) {
+        rowk[buf][tj + TG * c] = S[rk][c];
+        xrow[buf][tj + TG * c] = X[rk][c];
       }
     }
     __syncthreads();
-    const double piv = rowk[k];
+    const double piv = rowk[buf][k];
     const bool dk = !(piv > dep_tol);
     const double ir = dk ? 1.0 : rsq_nr(piv);
     const double ipiv = dk ? 0.0 : ir * ir;
-    double xr[6], sr[6];
+    double xr[NR], sr[NR];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const int j = tj + 16 * c;
-      xr[c] = xrow[j];
-      sr[c] = (j > k) ? rowk[j] : 0.0;
+    for (int c = 0; c < NR; ++c) {
+      const int j = tj + TG * c;
+      xr[c] = (TG * c <= k) ? xrow[buf][j] : 0.0;          // X row k is zero beyond column k
+      sr[c] = (TG * c + TG - 1 > k && j > k) ? rowk[buf][j] : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      const int i = ti + 16 * r;
-      const double mi = (i > k) ? rowk[i] * ipiv : 0.0;
+    for (int r = 0; r < NR; ++r) {
+      if (TG * r + TG - 1 < k) continue;                     // rows all before the pivot
+      const int i = ti + TG * r;
+      const double mi = (i > k) ? rowk[buf][i] * ipiv : 0.0;
       const double sc = (i == k) ? ir : 1.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        S[r][c] = fma(-mi, sr[c], S[r][c]);
-        X[r][c] = fma(-mi, xr[c], X[r][c]) * sc;
+      for (int c = 0; c < NR; ++c) {
+        if (TG * c + TG - 1 > k) S[r][c] = fma(-mi, sr[c], S[r][c]);
+        if (TG * c <= k) X[r][c] = fma(-mi, xr[c], X[r][c]) * sc;
       }
     }
     if (t == 0) depl[k] = dk ? 1 : 0;
-    __syncthreads();
   }
+  __syncthreads();
   // W[j][i] = X[i][j] / D[j]
 #pragma unroll
-  for (int r = 0; r < 6; ++r)
+  for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const int i = ti + 16 * r, j = tj + 16 * c;
+    for (int c = 0; c < NR; ++c) {
+      const int i = ti + TG * r, j = tj + TG * c;
       if (i < b && j < b) Wout[j * b + i] = Dn[j] > 0.0 ? X[r][c] / Dn[j] : 0.0;
     }
   if (t < b) dep[t] = depl[t];
@@ -647,7 +653,8 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
                   int* err) {
   CTM_REQUIRE(b >= 1 && b <= 96, "chol_inverse: b out of range");
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, ctx.stream, G, b, dep_tol, W, dep, err);
+  hipLaunchKernelGGL((chol_inv_kernel<32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol, W,
+                     dep, err);
   CTM_HIP(hipGetLastError());
 }
 
