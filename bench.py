@@ -92,17 +92,27 @@ def calibrate_copy(torch):
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(source):
     import hashlib
-    path = os.path.join(ROOT, "paper_1906_02220_amd", "csrc", "gemm_f64.hip")
+    path = os.path.join(ROOT, "paper_1906_02220_amd", "csrc", source)
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(path):
-    """HBM bytes per launch of the n^3 GEMM from the counter summary (lines
-    'key: value'); None when the summary is missing or was taken on another
-    version of the GEMM source."""
+TRAFFIC = {  # counter summary and kernel source per precision mode
+    0: ("traffic_dgemm_rr_cut_D6_chi72.txt", "gemm_f64.hip"),
+    3: ("traffic_gemm_bf16s3_cut_D6_chi72.txt", "gemm_mixed.hip"),
+}
+
+
+def read_traffic(mode):
+    """HBM bytes per launch of the mode's n^3 product from its counter
+    summary (lines 'key: value'); None when there is none or it was taken on
+    another version of the kernel source."""
+    if mode not in TRAFFIC:
+        return None
+    name, source = TRAFFIC[mode]
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -111,7 +121,7 @@ def read_traffic(path):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("gemm_source_sha256_16") != kernel_source_hash():
+    if kv.get("gemm_source_sha256_16") != kernel_source_hash(source):
         return None
     try:
         return int(float(kv["hbm_bytes_per_launch"]))
@@ -168,7 +178,7 @@ def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[mode],
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[mode], 4),
-            "traffic": read_traffic(args.traffic) if mode == 0 else None,
+            "traffic": read_traffic(mode),
             "kernel": "%s (n x n x n, n=%d)" % (KERNEL_NAMES[mode], n),
             "flops_per_launch": per_launch, "launches": c0, "avg_launch_ms": round(avg_ms, 4)}
     torch.cuda.synchronize()
@@ -196,8 +206,6 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="0,1,3,4",
                     help="precision modes to time (0 FP64, 1 FP32, 3/4 BF16 slices); FP64 always runs")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_dgemm_rr_cut_D6_chi72.txt"),
-                    help="HBM-counter summary of the n^3 GEMM (bytes per launch)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()

@@ -93,6 +93,15 @@ const char* ctm_last_error(const ctm_context* ctx);
  * this context; NULL restores the context's own stream. */
 int ctm_context_set_stream(ctm_context* ctx, void* hip_stream);
 
+/* Replay warm sweeps from HIP graphs (on != 0; default off).  Once every
+ * projector SVD of an environment runs from a warm start and one such sweep
+ * has run normally, the next sweep is captured into a graph (the four moves
+ * and the corner-spectrum delta) and later sweeps replay it, which removes
+ * the per-kernel launch cost.  The counter-based generator that refills
+ * numerically dependent subspace columns then repeats its counters from
+ * sweep to sweep.  Sweeps with kernel timing switched on run normally. */
+int ctm_context_set_graphs(ctm_context* ctx, int on);
+
 /* Environment of a user-supplied site tensor a[u][l][d][r] (d^4 doubles,
  * host memory), chi >= 1, d >= 1.  Initial corners C = [[1]] and edges
  * T[0,:,0] = boundary (zero-padded to chi): after k sweeps in which no
@@ -125,6 +134,19 @@ void ctm_env_destroy(ctm_env* env);
  * environment valid) if tol > 0 was not reached, CTM_ENUMERIC on NaN/Inf or
  * an SVD failure. */
 int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double* delta);
+
+/* Sweeps of several independent environments at once (for example a scan
+ * over couplings or temperatures, Sec. III's CTMRG run per state).  Every
+ * round enqueues one sweep of each environment that has not converged, then
+ * waits for them: environments created on different contexts run
+ * concurrently on their contexts' streams, environments sharing a context
+ * run in turn.  Per environment the semantics are those of ctm_sweep.
+ * envs: count distinct environments; sweeps_done, delta: arrays of count
+ * (may be NULL).  Returns CTM_ENOTCONV if tol > 0 was not reached by every
+ * environment; on an error the message (kept on the first environment's
+ * context) names the environment, and every stream has drained. */
+int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol,
+                    int* sweeps_done, double* delta);
 
 /* One absorption move: direction 0 left, 1 up, 2 right, 3 down. */
 int ctm_move(ctm_env* env, int direction);

@@ -7,6 +7,8 @@
 #include <memory>
 #include <string>
 #include <utility>
+#include <vector>
+#include <cmath>
 
 #include "ctm.h"
 #include "engine.hpp"
@@ -176,6 +178,11 @@ int ctm_context_set_stream(ctm_context* ctx, void* s) {
   });
 }
 
+int ctm_context_set_graphs(ctm_context* ctx, int on) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] { ctx->c.use_graphs = (on != 0); });
+}
+
 int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
                         ctm_env** out) {
   if (!ctx) return CTM_EINVAL;
@@ -247,6 +254,69 @@ int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double
   if (rc != CTM_OK) return rc;
   if (status != CTM_OK) env->owner_c->last_error = "max_sweeps reached before tol";
   return status;
+}
+
+int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol, int* sweeps_done,
+                    double* delta) {
+  if (!envs || count < 0) return CTM_EINVAL;
+  if (count == 0) return CTM_OK;
+  for (int i = 0; i < count; ++i)
+    if (!envs[i]) return CTM_EINVAL;
+  std::vector<int> done(count, 0), active(count, 1), pending(count, 0);
+  std::vector<double> dl(count, INFINITY);
+  ctm::Context* errc = envs[0]->owner_c;
+  int cur = -1;
+  const int rc = guarded_c(errc, [&] {
+    CTM_REQUIRE(max_sweeps >= 0, "max_sweeps must be >= 0");
+    for (int i = 0; i < count; ++i)
+      for (int j = 0; j < i; ++j)
+        CTM_REQUIRE(envs[i] != envs[j], "an environment appears twice in the batch");
+    try {
+      for (int s = 0; s < max_sweeps; ++s) {
+        // enqueue one sweep of every active environment, then collect them:
+        // environments on different contexts run concurrently on their streams
+        for (int i = 0; i < count; ++i) {
+          if (!active[i]) continue;
+          cur = i;
+          CTM_HIP(hipSetDevice(envs[i]->owner_c->device));
+          envs[i]->e->sweep_enqueue();
+          pending[i] = 1;
+        }
+        int left = 0;
+        for (int i = 0; i < count; ++i) {
+          if (!pending[i]) continue;
+          cur = i;
+          CTM_HIP(hipSetDevice(envs[i]->owner_c->device));
+          CTM_HIP(hipStreamSynchronize(envs[i]->owner_c->stream));
+          pending[i] = 0;
+          dl[i] = envs[i]->e->sweep_finish("ctm_sweep_batch");
+          ++done[i];
+          if (tol > 0.0 && dl[i] < tol) active[i] = 0;
+          left += active[i];
+        }
+        if (left == 0) break;
+      }
+    } catch (const ctm::Error& e) {
+      // drain every stream before reporting, so that no work is left in flight
+      for (int i = 0; i < count; ++i) {
+        (void)hipSetDevice(envs[i]->owner_c->device);
+        (void)hipStreamSynchronize(envs[i]->owner_c->stream);
+      }
+      throw ctm::Error(e.code, "environment " + std::to_string(cur) + ": " + e.what());
+    }
+  });
+  for (int i = 0; i < count; ++i) {
+    if (sweeps_done) sweeps_done[i] = done[i];
+    if (delta) delta[i] = dl[i];
+  }
+  if (rc != CTM_OK) return rc;
+  if (tol > 0.0)
+    for (int i = 0; i < count; ++i)
+      if (!(dl[i] < tol)) {
+        errc->last_error = "max_sweeps reached before tol";
+        return CTM_ENOTCONV;
+      }
+  return CTM_OK;
 }
 
 int ctm_move(ctm_env* env, int direction) {

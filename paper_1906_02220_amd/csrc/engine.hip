@@ -53,6 +53,21 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
   if (opt.svd_iters <= 0) opt.svd_iters = 2;
   if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 5;
   alloc();
+  CTM_HIP(hipHostMalloc((void**)&hbox, 64, hipHostMallocDefault));
+}
+
+Env::~Env() {
+  drop_graph();
+  if (hbox) (void)hipHostFree(hbox);
+}
+
+void Env::drop_graph() {
+  if (gexec) {
+    (void)hipStreamSynchronize(ctx.stream);
+    (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+  warm_eager_done = false;
 }
 
 void Env::alloc() {
@@ -98,6 +113,8 @@ void Env::alloc() {
   spec_old.alloc(4ull * chi * sizeof(double));
   scal.alloc(64 * sizeof(double));
   iflags.alloc((8 + (size_t)b) * sizeof(int));
+  rngc.alloc(2 * sizeof(unsigned long long));
+  fill_zero(ctx, (double*)rngc.p, 2);
   E.alloc(dd4 * sizeof(double));
   E8.alloc(dd4 * sizeof(double));
   fill_zero(ctx, logs.d(), 8);
@@ -106,6 +123,7 @@ void Env::alloc() {
 }
 
 void Env::set_site_tensor_dev(const double* a_dev) {
+  drop_graph();
   copy_dev(ctx, arot[0].d(), a_dev, (size_t)d * d * d * d);
   const long long dims[4] = {d, d, d, d};
   const int rot[4] = {3, 0, 1, 2};
@@ -152,6 +170,7 @@ void Env::build_purification_dev(const double* A, const double* B, int D_, int D
 
 // a3: C_i = [[1]], T_i[0,:,0] = boundary vector, zero-padded to chi.
 void Env::init_boundary() {
+  drop_graph();
   std::vector<double> bvec = opt.boundary;
   if (bvec.empty()) {
     bvec.assign(d, 0.0);
@@ -219,8 +238,10 @@ void Env::orth(double* Z, double* Q, int passes) {
     gemm_f64(ctx, b, b, n, 1.0, colmajor(src, b), rowmajor(src, b), 0.0, out_rowmajor(G.d(), b));
     chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err);
     gemm_f64(ctx, n, b, b, 1.0, rowmajor(src, b), rowmajor(Wm.d(), b), 0.0, out_rowmajor(dst, b));
-    refill_columns(ctx, dst, b, n, b, dep, opt.seed, rng_ctr);
-    rng_ctr += (unsigned long long)n * b;
+    unsigned long long* rc = (unsigned long long*)rngc.p;
+    refill_columns(ctx, dst, b, n, b, dep, opt.seed ^ 0x5deece66dULL, rc + rng_slot,
+                   rc + (rng_slot ^ 1));
+    rng_slot ^= 1;
     src = dst;
   }
 }
@@ -345,23 +366,103 @@ void Env::reset_spectra() {
 // a8: sweeps (left, right, up, down) with the corner-spectrum criterion.
 int Env::sweep(int max_sweeps, double tol, int* done, double* delta_out) {
   CTM_REQUIRE(max_sweeps >= 0, "max_sweeps must be >= 0");
-  static const int order[4] = {0, 2, 1, 3};
   double delta = INFINITY;
   int s = 0;
-  int* err = (int*)iflags.p + 1;
   for (; s < max_sweeps; ++s) {
-    for (int i = 0; i < 4; ++i) move(order[i]);
-    jacobi_svd(ctx, Call.d(), chi, nullptr, spec_s.d(), nullptr, err, 4, (long long)chi * chi, chi);
-    spectra_delta(ctx, spec_s.d(), spec_old.d(), chi, scal.d());
-    CTM_HIP(hipMemcpyAsync(&delta, scal.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-    check_flags("ctm_sweep");
-    ++sweeps_done;
+    sweep_enqueue();
+    CTM_HIP(hipStreamSynchronize(ctx.stream));
+    delta = sweep_finish("ctm_sweep");
     if (tol > 0.0 && delta < tol) { ++s; break; }
   }
   if (done) *done = s;
   if (delta_out) *delta_out = delta;
   if (tol > 0.0 && !(delta < tol)) return 1;
   return 0;
+}
+
+void Env::sweep_body() {
+  static const int order[4] = {0, 2, 1, 3};
+  int* err = (int*)iflags.p + 1;
+  for (int i = 0; i < 4; ++i) move(order[i]);
+  jacobi_svd(ctx, Call.d(), chi, nullptr, spec_s.d(), nullptr, err, 4, (long long)chi * chi, chi);
+  spectra_delta(ctx, spec_s.d(), spec_old.d(), chi, scal.d());
+}
+
+// A sweep may be captured once every direction runs warm (so the host takes
+// the same branches on every sweep) and a warm sweep has already run eagerly
+// (so every workspace the sweep needs exists and no allocation can fall into
+// the capture).  Timing events are not captured.
+bool Env::graph_ready() const {
+  if (!ctx.use_graphs || ctx.timing || !warm_eager_done) return false;
+  if (n > jacobi_max_b(true))
+    for (int k = 0; k < 4; ++k)
+      if (!warm_ok[k]) return false;
+  return true;
+}
+
+void Env::capture_graph() {
+  hipGraph_t g = nullptr;
+  const int slot0 = rng_slot;
+  CTM_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
+  try {
+    sweep_body();
+    if (rng_slot != slot0) {
+      // an odd number of refills: move the counter back to the slot the
+      // next replay reads
+      copy_dev(ctx, (double*)rngc.p + slot0, (const double*)rngc.p + rng_slot, 1);
+      rng_slot = slot0;
+    }
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(ctx.stream, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    (void)hipGetLastError();
+    throw;
+  }
+  CTM_HIP(hipStreamEndCapture(ctx.stream, &g));
+  const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    gexec = nullptr;
+    CTM_HIP(e);
+  }
+  g_splitk = ctx.splitk_ws.p;
+  g_mixed = ctx.mixed_ws.p;
+}
+
+void Env::sweep_enqueue() {
+  if (graph_ready()) {
+    // the captured workspaces must still be the context's (a larger request
+    // from another call reallocates them)
+    if (gexec && (g_splitk != ctx.splitk_ws.p || g_mixed != ctx.mixed_ws.p)) {
+      (void)hipStreamSynchronize(ctx.stream);
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    if (!gexec) capture_graph();
+    CTM_HIP(hipGraphLaunch(gexec, ctx.stream));
+    e_valid = false;
+  } else {
+    bool warm = true;
+    if (n > jacobi_max_b(true))
+      for (int k = 0; k < 4; ++k) warm = warm && warm_ok[k];
+    sweep_body();
+    if (warm) warm_eager_done = true;
+  }
+  CTM_HIP(hipMemcpyAsync(hbox, scal.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  CTM_HIP(hipMemcpyAsync(hbox + 1, iflags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+}
+
+double Env::sweep_finish(const char* where) {
+  const int* hf = (const int*)(hbox + 1);
+  if (hf[0] || hf[1]) {
+    const bool nonfinite = hf[0] != 0;
+    fill_zero_int(ctx, (int*)iflags.p, 2);
+    throw Error(-4, std::string(where) + (nonfinite ? ": non-finite or vanishing environment tensor"
+                                                    : ": projector SVD failed"));
+  }
+  ++sweeps_done;
+  return hbox[0];
 }
 
 // a9: the ring E[u,l,x,r] of the eight environment tensors around one site,
@@ -550,6 +651,7 @@ void Env::get(double* C, double* T, double* hl) {
 }
 
 void Env::set(const double* C, const double* T, const double* hl) {
+  drop_graph();
   CTM_HIP(hipMemcpyAsync(Call.p, C, Call.bytes, hipMemcpyHostToDevice, ctx.stream));
   CTM_HIP(hipMemcpyAsync(Tall.p, T, Tall.bytes, hipMemcpyHostToDevice, ctx.stream));
   CTM_HIP(hipMemcpyAsync(logs.p, hl, 8 * sizeof(double), hipMemcpyHostToDevice, ctx.stream));

@@ -18,6 +18,9 @@ struct EnvOptions {
 class Env {
  public:
   Env(Context& ctx, int d, int chi, const EnvOptions& opt);
+  ~Env();
+  Env(const Env&) = delete;
+  Env& operator=(const Env&) = delete;
   // classical / user site tensor (device pointer, d^4)
   void set_site_tensor_dev(const double* a_dev);
   // purification pair (device pointers [2][2][x][y][z])
@@ -26,6 +29,14 @@ class Env {
 
   void move(int k);              // left move in the frame rotated k times
   int sweep(int max_sweeps, double tol, int* done, double* delta);
+  // One sweep without waiting for it: the four moves and the corner-spectrum
+  // delta (replayed from a captured HIP graph when the context allows graphs
+  // and the previous sweep was a warm one), then asynchronous copies of the
+  // delta and the error flags to pinned host memory.
+  void sweep_enqueue();
+  // After ctx.stream has drained: the delta of that sweep; throws on a
+  // numerical failure the kernels flagged.
+  double sweep_finish(const char* where);
 
   double kappa();
   void log_z(double* log_abs, double* sign);
@@ -45,6 +56,10 @@ class Env {
 
  private:
   void alloc();
+  void sweep_body();
+  bool graph_ready() const;
+  void capture_graph();
+  void drop_graph();
   void corner(int f);
   void svd_top(const double* Mt, int k);
   void orth(double* Z, double* Q, int passes);
@@ -70,7 +85,15 @@ class Env {
   DevBuf iflags;                  // [0] numeric, [1] svd, [2..] dependency flags
   DevBuf E, E8;
   bool e_valid = false;
-  unsigned long long rng_ctr = 0;
+  unsigned long long rng_ctr = 0;  // counter of the cold-start draws
+  DevBuf rngc;                     // two device slots of the refill counter
+  int rng_slot = 0;                // slot the next refill reads
+  // graph of one warm sweep and the context workspaces it was captured with
+  hipGraphExec_t gexec = nullptr;
+  const void* g_splitk = nullptr;
+  const void* g_mixed = nullptr;
+  bool warm_eager_done = false;  // a warm sweep ran eagerly (workspaces sized)
+  double* hbox = nullptr;        // pinned host memory: delta, then two int flags
 };
 
 }  // namespace ctm

@@ -185,13 +185,32 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
 
 }  // namespace
 
+// Tile of a workgroup, XCD-aware.  Workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup w runs on XCD w % 8), and each XCD has its own
+// L2.  Tile t = (w % 8) * (T / 8) + ... gives every XCD a contiguous range of
+// the tile order, and that order walks G tile rows at a time, so one XCD
+// touches about G row panels of A and range / G column panels of B instead
+// of all of them.
+template <int G>
+__device__ inline void xcd_tile(int w, int ntm, int ntn, int& tm, int& tn) {
+  const int T = ntm * ntn;
+  const int x = w & 7, loc = w >> 3;
+  const int t = x * (T >> 3) + min(x, T & 7) + loc;
+  const int grp = t / (G * ntn);
+  const int first = grp * G;
+  const int gs = min(ntm - first, G);
+  const int r = t - grp * G * ntn;
+  tm = first + r % gs;
+  tn = r / gs;
+}
+
 // ------------------------------------------------------------ BF16 slice GEMM
 
 // C (M x N, row stride ldc, FP64) = A B from the slices Aq[S][M][Kp] and
 // Bq[S][N][Kp] (B stored transposed) and the row / column maxima.  128 x 128
 // tile, 8 waves as 4 x 2, each wave 32 x 64 (2 x 4 MFMA tiles); K steps of
 // 32 through double-buffered LDS with a register prefetch of the next step.
-template <int S, int TAG>
+template <int S, int TAG, int XG = 8>
 __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     int M, int N, int Kp, const __bf16* __restrict__ Aq, const __bf16* __restrict__ Bq,
     const double* __restrict__ amax, const double* __restrict__ bmax, double* __restrict__ C,
@@ -202,8 +221,9 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][BN * PITCH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
-  const int ntn = (N + BN - 1) / BN;
-  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  int tm, tn;
+  xcd_tile<XG>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
   const long long aslab = (long long)M * Kp, bslab = (long long)N * Kp;
   // global -> register mapping: thread t loads 16 bytes (8 k) of row t / 4
   const int lrow = tid >> 2, lk = (tid & 3) * 8;

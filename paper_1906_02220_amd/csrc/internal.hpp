@@ -75,6 +75,7 @@ struct Context {
   hipStream_t stream = nullptr;
   std::string last_error;
   bool timing = false;
+  bool use_graphs = false;  // replay warm sweeps from captured HIP graphs
   TimingClass tcls[3];
   // events pending resolution: (class, start, stop, flops)
   struct Pending { int cls; hipEvent_t a, b; double flops; };
@@ -165,9 +166,13 @@ void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
                   int* err);
 // Replace the columns j with dep[j] != 0 of an n x b row-major Q by standard
-// normal numbers from the counter-based generator.
+// normal numbers from the counter-based generator, starting at the counter
+// *counter_in (device memory); *counter_out (another device slot) receives
+// the counter advanced by n * b.  Keeping the counter on the device makes a
+// replayed graph draw the same numbers as the eager run it was captured from.
 void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
-                    unsigned long long seed, unsigned long long counter);
+                    unsigned long long seed, const unsigned long long* counter_in,
+                    unsigned long long* counter_out);
 // Scale every column of an n x b row-major Z to unit 2-norm.
 void normalise_columns(Context& ctx, double* Z, int ldz, int n, int b);
 // One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T,

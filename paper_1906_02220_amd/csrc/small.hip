@@ -3,6 +3,9 @@
 // orthonormalise the subspace of the truncated projector SVD, the one-sided
 // Jacobi SVD of small square matrices, and column scalings.
 #include <cfloat>
+#include <mutex>
+#include <utility>
+#include <vector>
 #include <algorithm>
 #include <cmath>
 
@@ -263,9 +266,14 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
 // Replace the columns j with dep[j] != 0 of an n x b row-major Q by
 // standard normal numbers.
 __global__ void refill_kernel(double* Q, int ldq, int n, int b, const int* __restrict__ dep,
-                              unsigned long long seed, unsigned long long ctr) {
+                              unsigned long long seed,
+                              const unsigned long long* __restrict__ ctr_in,
+                              unsigned long long* __restrict__ ctr_out) {
   __shared__ int dl[128];
   for (int j = threadIdx.x; j < b; j += blockDim.x) dl[j] = dep[j];
+  const unsigned long long ctr = *ctr_in;
+  // the next call reads the other slot, so no block can see this write early
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = ctr + (unsigned long long)n * b;
   __syncthreads();
   const long long total = (long long)n * b;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
@@ -556,10 +564,20 @@ __global__ void spectra_delta_kernel(const double* s, double* old, int chi, doub
 
 // Raise the dynamic-LDS limit of a kernel to `bytes` when above the 64 KB
 // default (gfx950 has 160 KB of LDS per CU).
+// Raise a kernel's dynamic-LDS limit once per (kernel, size) and process:
+// later calls, including those made while a stream is being captured into a
+// graph, issue no runtime call.
 void allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return;
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> done;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : done)
+    if (e.first == fn && e.second >= bytes) return;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     (void)hipGetLastError();
+  else
+    done.push_back({fn, bytes});
 }
 
 inline int grid_for(size_t n, int block = 256, int cap = 4096) {
@@ -659,11 +677,12 @@ void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* 
 }
 
 void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
-                    unsigned long long seed, unsigned long long counter) {
+                    unsigned long long seed, const unsigned long long* counter_in,
+                    unsigned long long* counter_out) {
   CTM_REQUIRE(b >= 1 && b <= 128, "refill_columns: b out of range");
   const size_t total = (size_t)n * b;
   hipLaunchKernelGGL(refill_kernel, dim3(grid_for(total, 256, 1024)), dim3(256), 0, ctx.stream, Q,
-                     ldq, n, b, dep, seed, counter);
+                     ldq, n, b, dep, seed, counter_in, counter_out);
   CTM_HIP(hipGetLastError());
 }
 

@@ -60,6 +60,7 @@ SIGNATURES = {
     "ctm_context_destroy": (None, [_P]),
     "ctm_last_error": (ctypes.c_char_p, [_P]),
     "ctm_context_set_stream": (ctypes.c_int, [_P, _P]),
+    "ctm_context_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_env_init_tensor": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
     "ctm_env_init_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int,
@@ -67,6 +68,8 @@ SIGNATURES = {
                                                  ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
     "ctm_env_destroy": (None, [_P]),
     "ctm_sweep": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _I, _D]),
+    "ctm_sweep_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, _I, _D]),
     "ctm_move": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_norm": (ctypes.c_int, [_P, _D]),
     "ctm_log_z": (ctypes.c_int, [_P, _D, _D]),
@@ -154,6 +157,10 @@ class Context:
     def set_stream(self, stream_ptr):
         self.check(self.lib.ctm_context_set_stream(self.h, _P(stream_ptr)), "set_stream")
 
+    def graphs(self, on=True):
+        """Replay warm sweeps of this context's environments from HIP graphs."""
+        self.check(self.lib.ctm_context_set_graphs(self.h, 1 if on else 0), "set_graphs")
+
     def timing(self, on=True):
         self.check(self.lib.ctm_timing_enable(self.h, 1 if on else 0), "timing_enable")
 
@@ -178,6 +185,23 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def sweep_batch(envs, max_sweeps, tol=0.0):
+    """Sweeps of several environments at once (ctm_sweep_batch): environments
+    on different contexts run concurrently.  Returns (rc, sweeps_done, delta)
+    with one entry per environment."""
+    envs = list(envs)
+    n = len(envs)
+    if n == 0:
+        return CTM_OK, np.zeros(0, np.int32), np.zeros(0)
+    arr = (_P * n)(*[e.h for e in envs])
+    done = np.zeros(n, dtype=np.int32)
+    delta = np.zeros(n)
+    rc = load_library().ctm_sweep_batch(arr, n, max_sweeps, tol,
+                                        done.ctypes.data_as(_I), delta.ctypes.data_as(_D))
+    envs[0].ctx.check(rc, "ctm_sweep_batch")
+    return rc, done, delta
 
 
 class Environment:

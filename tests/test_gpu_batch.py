@@ -1,0 +1,127 @@
+"""Batched sweeps and graph replay.
+
+ctm_sweep_batch runs one sweep of every environment per round, with
+environments on different contexts overlapping on their streams; graph
+replay captures one warm sweep into a HIP graph.  Neither changes the
+arithmetic: every kernel of an environment runs in the same order with the
+same arguments, so the results must equal those of plain ctm_sweep calls
+exactly (the oracle parity of the plain path is covered elsewhere).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ctmrg as O
+from paper_1906_02220_amd import ctm, synth
+
+pytestmark = pytest.mark.gpu
+
+H = synth.bond_operator_real(synth.random_coefficients(6))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _env(ctx, D, chi, seed, gamma=2, **kw):
+    A, B = synth.random_purification(D, seed, gamma=gamma)
+    return ctm.Environment.from_purification(ctx, A, B, gamma, chi, **kw)
+
+
+def _state(env):
+    return env.norm(), env.expect(H), env.corner_spectra(), env.bond_metric()
+
+
+def _same(s1, s2):
+    k1, e1, sp1, E1 = s1
+    k2, e2, sp2, E2 = s2
+    assert k1 == k2
+    assert e1 == e2
+    assert np.array_equal(sp1, sp2)
+    assert np.array_equal(E1, E2)
+
+
+def test_graph_replay_matches_eager_sweep_by_sweep():
+    """D = 4, chi = 32 (subspace SVD with warm starts): every sweep replayed
+    from the graph, with observables computed eagerly between replays,
+    equals the eager sweep."""
+    say("case: graph replay D=4 chi=32 seed=1234, 8 sweeps")
+    ce, cg = ctm.Context(0), ctm.Context(0)
+    cg.graphs(True)
+    ee, eg = _env(ce, 4, 32, 1234), _env(cg, 4, 32, 1234)
+    for s in range(8):
+        r1, r2 = ee.sweep(1), eg.sweep(1)
+        assert r1 == r2
+        _same(_state(ee), _state(eg))
+    # a state change drops the graph; replay resumes after two warm sweeps
+    C, T, logs = ee.get()
+    ee.set(C, T, logs)
+    eg.set(C, T, logs)
+    for s in range(4):
+        assert ee.sweep(1) == eg.sweep(1)
+        _same(_state(ee), _state(eg))
+    ce.close()
+    cg.close()
+
+
+CASES = [(2, 12, 3, 2), (3, 20, 4, 1), (4, 32, 1234, 2), (2, 30, 5, 0)]
+
+
+def test_sweep_batch_matches_sequential():
+    """Four environments of different D and chi (direct-Jacobi and subspace
+    SVD paths, three bond types), each on its own context, two of them with
+    graph replay."""
+    say("case: batch of %d environments, 10 sweeps" % len(CASES))
+    ctxs = [ctm.Context(0) for _ in CASES]
+    for c in ctxs[::2]:
+        c.graphs(True)
+    batch = [_env(c, D, chi, seed, gamma) for c, (D, chi, seed, gamma) in zip(ctxs, CASES)]
+    rc, done, delta = ctm.sweep_batch(batch, 10, 0.0)
+    assert rc == ctm.CTM_OK and list(done) == [10] * len(CASES)
+    cs = ctm.Context(0)
+    for (D, chi, seed, gamma), eb, db in zip(CASES, batch, delta):
+        es = _env(cs, D, chi, seed, gamma)
+        rcs, ds, dels = es.sweep(10)
+        assert dels == db
+        _same(_state(eb), _state(es))
+    # one member against the oracle as well
+    A, B = synth.random_purification(3, 4, gamma=1)
+    oenv, a, _, _, _ = O.environment_from_purification(A, B, 1, 20, 10)
+    assert abs(batch[1].norm() / O.kappa(oenv, a) - 1.0) < 1e-10
+
+
+def test_sweep_batch_tolerance_and_sharing_a_context():
+    """With tol > 0 each environment stops on its own; environments may share
+    a context (they then run in turn on its stream)."""
+    say("case: batch with tol=1e-9 on one shared context")
+    ctx = ctm.Context(0)
+    tensors = [synth.ising_square_tensor(0.3), synth.ising_square_tensor(0.38)]
+    envs = [ctm.Environment.from_tensor(ctx, a, 8) for a in tensors]
+    rc, done, delta = ctm.sweep_batch(envs, 400, 1e-9)
+    say("  done %s delta %s" % (list(done), list(delta)))
+    assert rc == ctm.CTM_OK
+    assert np.all(delta < 1e-9)
+    for a, d, dl in zip(tensors, done, delta):
+        _, dr, delr = ctm.Environment.from_tensor(ctx, a, 8).sweep(400, 1e-9)
+        assert dr == d and delr == dl
+    one = ctm.Environment.from_tensor(ctx, tensors[0], 8)
+    rc, done, delta = ctm.sweep_batch([one], 2, 1e-300)
+    assert rc == ctm.CTM_ENOTCONV and list(done) == [2]
+
+
+def test_sweep_batch_reports_the_failing_environment():
+    say("case: batch with a non-finite environment")
+    c1, c2 = ctm.Context(0), ctm.Context(0)
+    good = _env(c1, 2, 12, 3)
+    A, B = synth.random_purification(2, 1)
+    A = A.copy()
+    A[0, 0, 0, 0, 0] = np.nan
+    bad = ctm.Environment.from_purification(c2, A, B, 2, 12)
+    with pytest.raises(ctm.CtmError) as ei:
+        ctm.sweep_batch([good, bad], 3, 0.0)
+    assert ei.value.code == ctm.CTM_ENUMERIC
+    assert "environment 1" in str(ei.value)
+    # the good environment is still usable
+    assert np.isfinite(good.norm())
