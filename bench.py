@@ -24,6 +24,15 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
+# Concurrent environments of the batch measurement each run on their own
+# stream; HIP maps streams onto this many hardware queues (its default is 4).
+# Set before HIP starts; at least 16, never above 32.
+try:
+    _q = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _q = 4
+os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(_q, 16)))
+
 PEAK_F64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
 
@@ -50,7 +59,7 @@ def executed_move_macs(chi, d):
     return corners + halves + proj + renorm
 
 
-def cpu_baseline(D, chi, seed, moves=2):
+def cpu_baseline(D, chi, seed, moves=20):
     """The FP64 oracle on the host cores: `moves` absorption moves from the
     boundary start at the benchmark shape (each with a full LAPACK SVD of the
     n x n cut matrix)."""
@@ -141,7 +150,7 @@ PRECISION_TEXT = {
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 3: 2500.0, 4: 2500.0}
 SLICE_PRODUCTS = {0: 1, 1: 1, 3: 6, 4: 10}
 KERNEL_NAMES = {0: "dgemm_rr<96,96,16,2,2,0>", 1: "gemm_f32x1_kernel<0>",
-                3: "gemm_bf16s_kernel<3,0>", 4: "gemm_bf16s_kernel<4,0>"}
+                3: "gemm_bf16s_kernel<3,0,8>", 4: "gemm_bf16s_kernel<4,0,8>"}
 
 
 def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
@@ -194,6 +203,52 @@ def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
             "roofline": roof, "fu_ms": fu_ms, "kappa": kappa, "energy_bond": e_h}
 
 
+def run_batch(ctm, torch, synth, count, warm, steps):
+    """Batched sweeps: `count` independent purifications with (D, chi) drawn
+    uniformly from {4,5,6,7} x {32,48,72,96} (seed 777), A and B i.i.d.
+    N(0,1) in FP32 (seed 778 + i), scaled to unit max-abs, contractions in
+    the FP32 mode.  Timed: `steps` sweeps of the whole batch after `warm`,
+    with the environments in turn on one context, concurrently on one
+    context each, and concurrently with autotuned tilings and graph replay."""
+    rng = np.random.default_rng(777)
+    Ds = rng.choice([4, 5, 6, 7], size=count).tolist()
+    chis = rng.choice([32, 48, 72, 96], size=count).tolist()
+    cfg = list(zip(Ds, chis))
+    work = sum(2.0 * move_macs(chi, D * D) * 4 for D, chi in cfg)
+    out = {"workload": "%d purifications, (D, chi) uniform on {4,5,6,7} x {32,48,72,96} "
+                       "(seed 777), FP32 entries, FP32 contraction mode" % count,
+           "envs": [[int(D), int(chi)] for D, chi in cfg], "sweeps_timed": steps,
+           "unit": "GFLOP/s (sum over the batch, algorithmic)"}
+    for name, one_ctx, tune, graphs in (("in_turn", True, False, False),
+                                        ("concurrent", False, False, False),
+                                        ("concurrent_autotuned_graphs", False, True, True)):
+        ctxs = [ctm.Context(0)] if one_ctx else [ctm.Context(0) for _ in cfg]
+        for c in ctxs:
+            c.autotune(tune)
+            c.graphs(graphs)
+        envs = []
+        for i, (D, chi) in enumerate(cfg):
+            A, B = synth.random_purification(D, 778 + i, dtype=np.float32)
+            envs.append(ctm.Environment.from_purification(ctxs[0 if one_ctx else i], A, B, 2, chi,
+                                                          precision=ctm.CTM_PREC_F32))
+        ctm.sweep_batch(envs, warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctm.sweep_batch(envs, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": round(work * steps / dt / 1e9, 2),
+                     "ms_per_batch_sweep": round(1e3 * dt / steps, 3)}
+        log("bench: batch %s: %.1f ms per batch sweep" % (name, 1e3 * dt / steps))
+        for e in envs:
+            e.close()
+        for c in ctxs:
+            c.close()
+    out["speedup_vs_in_turn"] = round(out["concurrent_autotuned_graphs"]["value"] /
+                                      out["in_turn"]["value"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +259,8 @@ def main():
     ap.add_argument("--chi", type=int, default=72)
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="environments of the batched-sweep measurement (0: skip it)")
     ap.add_argument("--modes", default="0,1,3,4",
                     help="precision modes to time (0 FP64, 1 FP32, 3/4 BF16 slices); FP64 always runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -288,6 +345,8 @@ def main():
         "kappa": h["kappa"],
         "energy_bond": h["energy_bond"],
     }
+    if args.batch > 0:
+        out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(D, chi, seed)

@@ -93,6 +93,14 @@ const char* ctm_last_error(const ctm_context* ctx);
  * this context; NULL restores the context's own stream. */
 int ctm_context_set_stream(ctm_context* ctx, void* hip_stream);
 
+/* Autotune the tile shape of the large FP64 and FP32 products (on != 0;
+ * default off): the first product of each shape on this context runs every
+ * candidate tiling (96 x 96, 128 x 128, 64 x 64 output tiles) three times,
+ * keeps the fastest, and later products of that shape use it.  The
+ * candidates accumulate in the same order, so results do not depend on the
+ * choice. */
+int ctm_context_set_autotune(ctm_context* ctx, int on);
+
 /* Replay warm sweeps from HIP graphs (on != 0; default off).  Once every
  * projector SVD of an environment runs from a warm start and one such sweep
  * has run normally, the next sweep is captured into a graph (the four moves

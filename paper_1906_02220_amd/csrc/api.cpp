@@ -178,6 +178,11 @@ int ctm_context_set_stream(ctm_context* ctx, void* s) {
   });
 }
 
+int ctm_context_set_autotune(ctm_context* ctx, int on) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] { ctx->c.autotune = (on != 0); });
+}
+
 int ctm_context_set_graphs(ctm_context* ctx, int on) {
   if (!ctx) return CTM_EINVAL;
   return guarded(ctx, [&] { ctx->c.use_graphs = (on != 0); });

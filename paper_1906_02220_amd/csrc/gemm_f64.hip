@@ -22,11 +22,13 @@
 // dgemm_rr: 16-byte global loads, A staged [m][k] and B [k][n] in LDS, and a
 // 96 x 96 tile with 2 x 2 waves, so three workgroups share a CU (53 KB LDS
 // each) and an n = 2592 product (27 x 27 tiles) runs as one pass over the
-// 256 CUs.  Its template tag only separates the cut-matrix products from
+// 256 CUs.  Tiles are assigned XCD by XCD (see xcd_tile), which cuts the L2
+// misses on re-read operand panels.  Its template tag only separates the cut-matrix products from
 // the other users in kernel traces.
 #include "internal.hpp"
 
 #include <cstdint>
+#include <functional>
 
 namespace ctm {
 
@@ -61,8 +63,9 @@ __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
   __shared__ double Bs[2][BK * SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
-  const int ntn = (N + BN - 1) / BN;
-  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
+  int tm, tn;
+  xcd_tile<8>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
   A += blockIdx.y * abs_;
   B += blockIdx.y * bbs;
   const int kbeg = blockIdx.z * kchunk;
@@ -372,6 +375,32 @@ void launch_cfg(Context& ctx, bool akc, bool bnc, dim3 grid, int M, int N, int K
 
 }  // namespace
 
+int pick_variant(Context& ctx, int kind, int M, int N, int K, int cls, int nvariants,
+                 const std::function<void(int)>& run) {
+  if (!ctx.autotune || nvariants <= 1) return 0;
+  const auto key = std::make_tuple(kind, M, N, K, cls);
+  auto it = ctx.tuned.find(key);
+  if (it != ctx.tuned.end()) return it->second;
+  hipEvent_t e0 = ctx.get_event(), e1 = ctx.get_event();
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int v = 0; v < nvariants; ++v) {
+    run(v);
+    CTM_HIP(hipEventRecord(e0, ctx.stream));
+    run(v);
+    run(v);
+    CTM_HIP(hipEventRecord(e1, ctx.stream));
+    CTM_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    CTM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (v == 0 || ms < best_ms) { best = v; best_ms = ms; }
+  }
+  ctx.event_pool.push_back(e0);
+  ctx.event_pool.push_back(e1);
+  ctx.tuned[key] = best;
+  return best;
+}
+
 void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, double beta,
               ViewOut C, int batch, int cls) {
   CTM_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 1, "gemm: negative size");
@@ -422,8 +451,34 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
       }
       W = ctx.splitk_ws.d();
     }
-    const dim3 grid((unsigned)(tiles / batch), batch, ksplit), block(256);
     const int lda = (int)A.rs, ldb = (int)B.rs, ldc = (int)C.rs;
+    if (ksplit == 1 && ctx.autotune) {
+      // tile candidates: 96 x 96 (2 x 2 waves), 128 x 128 (4 x 2), 64 x 64 (2 x 2);
+      // all accumulate K in the same order, so the choice never changes C
+      auto run = [&](int v) {
+        const int bm = v == 1 ? 128 : (v == 2 ? 64 : 96);
+        const dim3 g((unsigned)(((M + bm - 1) / bm) * ((N + bm - 1) / bm)), batch, 1);
+#define CTM_RR(BM_, WGM_, WGN_)                                                                   \
+  do {                                                                                           \
+    if (cls == 0)                                                                                \
+      hipLaunchKernelGGL((dgemm_rr<BM_, BM_, BK, WGM_, WGN_, 0>), g, dim3(WGM_ * WGN_ * 64), 0,    \
+                         ctx.stream, M, N, K, A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, 1, K, \
+                         nullptr);                                                              \
+    else                                                                                         \
+      hipLaunchKernelGGL((dgemm_rr<BM_, BM_, BK, WGM_, WGN_, 1>), g, dim3(WGM_ * WGN_ * 64), 0,    \
+                         ctx.stream, M, N, K, A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, 1, K, \
+                         nullptr);                                                              \
+  } while (0)
+        if (v == 1) CTM_RR(128, 4, 2);
+        else if (v == 2) CTM_RR(64, 2, 2);
+        else CTM_RR(96, 2, 2);
+#undef CTM_RR
+        CTM_HIP(hipGetLastError());
+      };
+      run(pick_variant(ctx, 0, M, N, K, cls, 3, run));
+      return;
+    }
+    const dim3 grid((unsigned)(tiles / batch), batch, ksplit), block(256);
     if (cls == 0)
       hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, 0>), grid, block, 0, ctx.stream, M, N, K,
                          A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W);

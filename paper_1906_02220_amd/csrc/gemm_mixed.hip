@@ -185,25 +185,6 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
 
 }  // namespace
 
-// Tile of a workgroup, XCD-aware.  Workgroups are dispatched round-robin
-// over the 8 XCDs (workgroup w runs on XCD w % 8), and each XCD has its own
-// L2.  Tile t = (w % 8) * (T / 8) + ... gives every XCD a contiguous range of
-// the tile order, and that order walks G tile rows at a time, so one XCD
-// touches about G row panels of A and range / G column panels of B instead
-// of all of them.
-template <int G>
-__device__ inline void xcd_tile(int w, int ntm, int ntn, int& tm, int& tn) {
-  const int T = ntm * ntn;
-  const int x = w & 7, loc = w >> 3;
-  const int t = x * (T >> 3) + min(x, T & 7) + loc;
-  const int grp = t / (G * ntn);
-  const int first = grp * G;
-  const int gs = min(ntm - first, G);
-  const int r = t - grp * G * ntn;
-  tm = first + r % gs;
-  tn = r / gs;
-}
-
 // ------------------------------------------------------------ BF16 slice GEMM
 
 // C (M x N, row stride ldc, FP64) = A B from the slices Aq[S][M][Kp] and
@@ -330,19 +311,24 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
 // C = A B with FP64 operands rounded to FP32 on the way into LDS, FP32 MFMA
 // and FP32 accumulation; same staging as the FP64 row-major kernel (96 x 96
 // tile, 2 x 2 waves, 16-byte global loads, double-buffered LDS).
-template <int TAG>
-__global__ __launch_bounds__(256) void gemm_f32x1_kernel(int M, int N, int K,
-                                                         const double* __restrict__ A, int lda,
-                                                         const double* __restrict__ B, int ldb,
-                                                         double* __restrict__ C, int ldc) {
-  constexpr int BM = 96, BN = 96, BK = 16, NT = 256;
-  constexpr int WM = 48, WN = 48, TI = 3, TJ = 3;
+template <int BM, int BN, int WGM, int WGN, int TAG>
+__global__ __launch_bounds__(WGM * WGN * 64) void gemm_f32x1_kernel(int M, int N, int K,
+                                                                    const double* __restrict__ A,
+                                                                    int lda,
+                                                                    const double* __restrict__ B,
+                                                                    int ldb,
+                                                                    double* __restrict__ C,
+                                                                    int ldc) {
+  constexpr int BK = 16, NT = WGM * WGN * 64;
+  constexpr int WM = BM / WGM, WN = BN / WGN, TI = WM / 16, TJ = WN / 16;
+  static_assert(TI * 16 == WM && TJ * 16 == WN, "wave tile must be a multiple of 16");
+  static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "pair mapping");
   constexpr int SA = BK + 1, SB = BN + 1;
   constexpr int AV = BM * BK / 2 / NT, BV = BK * BN / 2 / NT;
   __shared__ float As[2][BM * SA];
   __shared__ float Bs[2][BK * SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
   const int ntn = (N + BN - 1) / BN;
   const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
   const bool full_m = (m0 + BM <= M), full_n = (n0 + BN <= N);
@@ -501,15 +487,28 @@ void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View 
   const int tag = cls == 0 ? 0 : 1;
   if (mode == CTM_PREC_F32) {
     ScopedTimer t0(ctx, cls == 0 ? 0 : -1, flops);
-    const long long tiles = (long long)((M + 95) / 96) * ((N + 95) / 96);
-    CTM_REQUIRE(tiles <= i32, "gemm_mixed: grid too large");
-    if (tag == 0)
-      hipLaunchKernelGGL((gemm_f32x1_kernel<0>), dim3((unsigned)tiles), dim3(256), 0, ctx.stream,
-                         M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);
-    else
-      hipLaunchKernelGGL((gemm_f32x1_kernel<1>), dim3((unsigned)tiles), dim3(256), 0, ctx.stream,
-                         M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);
-    CTM_HIP(hipGetLastError());
+    CTM_REQUIRE((long long)((M + 63) / 64) * ((N + 63) / 64) <= i32, "gemm_mixed: grid too large");
+    // tile candidates: 96 x 96 (2 x 2 waves), 128 x 128 (4 x 2), 64 x 64 (2 x 2), all with the
+    // same K order; the autotuner (when on) keeps the fastest per shape
+    auto run = [&](int v) {
+      const int bm = v == 1 ? 128 : (v == 2 ? 64 : 96);
+      const dim3 g((unsigned)(((M + bm - 1) / bm) * ((N + bm - 1) / bm)));
+#define CTM_F32(BM_, WGM_, WGN_)                                                                   \
+  do {                                                                                            \
+    if (tag == 0)                                                                                 \
+      hipLaunchKernelGGL((gemm_f32x1_kernel<BM_, BM_, WGM_, WGN_, 0>), g, dim3(WGM_ * WGN_ * 64), 0, \
+                         ctx.stream, M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);     \
+    else                                                                                          \
+      hipLaunchKernelGGL((gemm_f32x1_kernel<BM_, BM_, WGM_, WGN_, 1>), g, dim3(WGM_ * WGN_ * 64), 0, \
+                         ctx.stream, M, N, K, A.p, (int)A.rs, B.p, (int)B.rs, C.p, (int)C.rs);     \
+  } while (0)
+      if (v == 1) CTM_F32(128, 4, 2);
+      else if (v == 2) CTM_F32(64, 2, 2);
+      else CTM_F32(96, 2, 2);
+#undef CTM_F32
+      CTM_HIP(hipGetLastError());
+    };
+    run(pick_variant(ctx, 1, M, N, K, cls, 3, run));
   } else if (mode == CTM_PREC_BF16X3) {
     run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, C.rs, cls);
   } else {

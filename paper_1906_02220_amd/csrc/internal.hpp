@@ -7,6 +7,9 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+#include <functional>
+#include <map>
+#include <tuple>
 
 namespace ctm {
 
@@ -76,6 +79,9 @@ struct Context {
   std::string last_error;
   bool timing = false;
   bool use_graphs = false;  // replay warm sweeps from captured HIP graphs
+  bool autotune = false;    // time the kernel variants of each product shape once
+  // fastest variant per (kind, M, N, K, timing class)
+  std::map<std::tuple<int, int, int, int, int>, int> tuned;
   TimingClass tcls[3];
   // events pending resolution: (class, start, stop, flops)
   struct Pending { int cls; hipEvent_t a, b; double flops; };
@@ -109,6 +115,25 @@ struct ScopedTimer {
   }
 };
 
+// Tile of a workgroup, XCD-aware.  Workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup w runs on XCD w % 8), and each XCD has its own
+// L2.  Tile t = (w % 8) * (T / 8) + ... gives every XCD a contiguous range of
+// the tile order, and that order walks G tile rows at a time, so one XCD
+// touches about G row panels of A and range / G column panels of B instead
+// of all of them.
+template <int G>
+__device__ inline void xcd_tile(int w, int ntm, int ntn, int& tm, int& tn) {
+  const int T = ntm * ntn;
+  const int x = w & 7, loc = w >> 3;
+  const int t = x * (T >> 3) + min(x, T & 7) + loc;
+  const int grp = t / (G * ntn);
+  const int first = grp * G;
+  const int gs = min(ntm - first, G);
+  const int r = t - grp * G * ntn;
+  tm = first + r % gs;
+  tn = r / gs;
+}
+
 // ---------------------------------------------------------------- matrices
 
 // A strided matrix view: element (i, j) of batch z is at
@@ -125,6 +150,14 @@ struct ViewOut {
 inline View rowmajor(const double* p, long long ld, long long bs = 0) { return {p, ld, 1, bs}; }
 inline View colmajor(const double* p, long long ld, long long bs = 0) { return {p, 1, ld, bs}; }
 inline ViewOut out_rowmajor(double* p, long long ld, long long bs = 0) { return {p, ld, 1, bs}; }
+
+// Variant of a product shape to launch: 0 unless the context autotunes; then
+// the first call of each (kind, M, N, K, cls) runs every variant once to warm
+// up and twice more between events, keeps the fastest, and later calls reuse
+// it.  run(v) launches variant v on ctx.stream; all variants of a kind must
+// compute the same result (the same K order per output element).
+int pick_variant(Context& ctx, int kind, int M, int N, int K, int cls, int nvariants,
+                 const std::function<void(int)>& run);
 
 // C = alpha * A(MxK) * B(KxN) + beta * C, FP64 MFMA, for `batch` matrices.
 // `cls` selects the timing class (-1: time only under class 1).

@@ -61,6 +61,7 @@ SIGNATURES = {
     "ctm_last_error": (ctypes.c_char_p, [_P]),
     "ctm_context_set_stream": (ctypes.c_int, [_P, _P]),
     "ctm_context_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ctm_context_set_autotune": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_env_init_tensor": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
     "ctm_env_init_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int,
@@ -160,6 +161,10 @@ class Context:
     def graphs(self, on=True):
         """Replay warm sweeps of this context's environments from HIP graphs."""
         self.check(self.lib.ctm_context_set_graphs(self.h, 1 if on else 0), "set_graphs")
+
+    def autotune(self, on=True):
+        """Time the candidate tilings of each large product shape once and keep the fastest."""
+        self.check(self.lib.ctm_context_set_autotune(self.h, 1 if on else 0), "set_autotune")
 
     def timing(self, on=True):
         self.check(self.lib.ctm_timing_enable(self.h, 1 if on else 0), "timing_enable")

@@ -125,3 +125,17 @@ def test_sweep_batch_reports_the_failing_environment():
     assert "environment 1" in str(ei.value)
     # the good environment is still usable
     assert np.isfinite(good.norm())
+
+
+@pytest.mark.parametrize("mode", [ctm.CTM_PREC_F64, ctm.CTM_PREC_F32])
+def test_autotuned_tilings_give_identical_results(mode):
+    """D = 4, chi = 32 (n = 512, 512 x 512 x 512 and 1024 x 256 x 256
+    products): the autotuner may pick any tiling, all accumulate in the same
+    order."""
+    say("case: autotune on vs off, precision mode %d" % mode)
+    c0, c1 = ctm.Context(0), ctm.Context(0)
+    c1.autotune(True)
+    e0 = _env(c0, 4, 32, 1234, precision=mode)
+    e1 = _env(c1, 4, 32, 1234, precision=mode)
+    assert e0.sweep(6) == e1.sweep(6)
+    _same(_state(e0), _state(e1))
