@@ -121,6 +121,21 @@ def honeycomb_ising_tensors(Kx, Ky, Kz):
     return A.copy(), A.copy()
 
 
+def honeycomb_ising_tensors_derivative(Kx, Ky, Kz, which):
+    """d(A, B)/dK_which of honeycomb_ising_tensors: V_g is replaced by its
+    derivative on the leg of bond type ``which``."""
+    Ks = [Kx, Ky, Kz]
+    Vs = [_bond_split(0.5 * k) for k in Ks]
+    k = 0.5 * Ks[which]
+    lam = np.array([2.0 * np.cosh(k), 2.0 * np.sinh(k)])
+    dlam = np.array([2.0 * np.sinh(k), 2.0 * np.cosh(k)])
+    U = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+    Vs[which] = U * (0.25 * dlam / np.sqrt(lam))[None, :]
+    dA = np.zeros((2, 2, 2, 2, 2))
+    dA[:, 0] = np.einsum('sx,sy,sz->sxyz', *Vs)
+    return dA.copy(), dA.copy()
+
+
 def singlet_tensors():
     """Infinite-temperature purification, D = 1: every pseudospin maximally
     entangled with its ancilla, A[s,a] = (delta_s0 delta_a1 - delta_s1 delta_a0)/sqrt 2."""
