@@ -209,6 +209,51 @@ int ctm_env_load(ctm_env* env, const char* path);
 /* Shape queries. */
 int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps);
 
+/* Statistics of the last gradient call. */
+typedef struct ctm_grad_info {
+  int moves;                 /* absorption moves differentiated */
+  int cg_iters_max;          /* most conjugate-gradient steps of one move */
+  long long cg_iters_total;  /* over all moves */
+  double ms_forward;         /* first forward pass, with checkpoints */
+  double ms_recompute;       /* forward re-runs of the checkpointed segments */
+  double ms_backward;        /* reverse pass */
+  double tape_bytes;         /* device memory of the per-move records */
+  double checkpoint_bytes;   /* device memory of the checkpoints */
+} ctm_grad_info;
+
+/* Gradient of L = w_log_kappa ln(kappa) + w_expect <O> with respect to the
+ * purification tensors A and B (reverse mode, written by hand), where kappa
+ * and <O> are those of ctm_norm and ctm_expect after `sweeps` sweeps from the
+ * boundary environment of the composite of A and B (Sec. III, Fig. 4).
+ * Inputs as ctm_env_init_purification; op / op_dim as ctm_expect (op may be
+ * null when w_expect = 0; *expect is then 0).  Outputs (host, caller-owned):
+ * *log_kappa, *expect, grad_A and grad_B (4 D^2 D_gamma each, the layout of
+ * A and B), *info when not null.
+ * The derivative is that of the fixed-sweep map with exact truncated SVDs
+ * of the cut matrices (the adjoint of the top-chi SVD includes the terms of
+ * the discarded subspace); the forward SVD is the subspace iteration of
+ * ctm_sweep, so raise svd_iters when the forward must match the exact SVD
+ * closely.  The environment state is checkpointed every checkpoint_every
+ * sweeps (<= 0: once at the start) and each segment is recomputed for the
+ * reverse pass; the result does not depend on checkpoint_every.  Device
+ * memory: about 4 (chi^2 (1 + d) + 2 n chi) doubles per move of a segment,
+ * n = chi d.  Needs precision CTM_PREC_F64 (CTM_EINVAL otherwise);
+ * CTM_ENUMERIC if a sweep fails as in ctm_sweep or kappa is not positive. */
+int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, int D, int D_gamma,
+                          int gamma, int chi, const ctm_opts* opts, int sweeps,
+                          int checkpoint_every, const double* op, int op_dim,
+                          double w_log_kappa, double w_expect, double* log_kappa,
+                          double* expect, double* grad_A, double* grad_B, ctm_grad_info* info);
+
+/* The same for a site tensor a (d^4, [u][l][d][r], as ctm_env_init_tensor):
+ * L = w_log_kappa ln(kappa) + w_expect <E, a_imp> / <E, a> with an impurity
+ * tensor a_imp (d^4; null when w_expect = 0), gradient dL/da in grad_a (d^4);
+ * a_imp is held fixed. */
+int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                    int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
+                    double w_expect, double* log_kappa, double* expect, double* grad_a,
+                    ctm_grad_info* info);
+
 /* Kernel timing over the calls since the last reset, measured with HIP
  * events on the context's stream around every launch of one kernel class.
  * cls 0: FP64 GEMMs of the n x n x n half-system and cut products;

@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "ctm.h"
+#include "adjoint.hpp"
 #include "engine.hpp"
 
 // The context state is shared by the context handle and every environment
@@ -322,6 +323,97 @@ int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol,
         return CTM_ENOTCONV;
       }
   return CTM_OK;
+}
+
+namespace {
+
+void fill_info(const ctm::GradStats& g, ctm_grad_info* info) {
+  if (!info) return;
+  info->moves = g.moves;
+  info->cg_iters_max = g.cg_iters_max;
+  info->cg_iters_total = g.cg_iters_total;
+  info->ms_forward = g.ms_forward;
+  info->ms_recompute = g.ms_recompute;
+  info->ms_backward = g.ms_backward;
+  info->tape_bytes = g.tape_bytes;
+  info->checkpoint_bytes = g.checkpoint_bytes;
+}
+
+}  // namespace
+
+int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, int D, int D_gamma,
+                          int gamma, int chi, const ctm_opts* opts, int sweeps,
+                          int checkpoint_every, const double* op, int op_dim,
+                          double w_log_kappa, double w_expect, double* log_kappa,
+                          double* expect, double* grad_A, double* grad_B, ctm_grad_info* info) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(A && B && grad_A && grad_B, "null argument");
+    CTM_REQUIRE(D >= 1 && D_gamma >= 1 && chi >= 1, "D, D_gamma and chi must be >= 1");
+    CTM_REQUIRE(gamma >= 0 && gamma <= 2, "gamma must be 0, 1 or 2");
+    CTM_REQUIRE(D <= 16, "D above 16 is not supported");
+    CTM_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
+    CTM_REQUIRE(op || w_expect == 0.0, "w_expect needs an operator");
+    CTM_REQUIRE(!op || op_dim == 4 || op_dim == 16, "op_dim must be 4 or 16");
+    const int d = D * D;
+    ctm::EnvOptions o = to_options(opts, d);
+    check_precision(o.precision);
+    CTM_REQUIRE(o.precision == CTM_PREC_F64, "gradients need precision CTM_PREC_F64");
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    ctm::Env env(ctx->c, d, chi, o);
+    const size_t sz = 4ull * D * D * D_gamma;
+    {
+      ctm::DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      env.build_purification_dev(dA.d(), dB.d(), D, D_gamma, gamma);
+    }
+    env.init_boundary();
+    ctm::Grad g(env, sweeps, checkpoint_every);
+    g.forward();
+    double lk = 0.0, ex = 0.0;
+    g.seed(w_log_kappa, w_expect, op, op_dim, nullptr, &lk, &ex);
+    g.backward();
+    g.grad_purification(A, B, D, D_gamma, gamma, grad_A, grad_B);
+    if (log_kappa) *log_kappa = lk;
+    if (expect) *expect = ex;
+    fill_info(g.stats, info);
+  });
+}
+
+int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                    int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
+                    double w_expect, double* log_kappa, double* expect, double* grad_a,
+                    ctm_grad_info* info) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(a && grad_a, "null argument");
+    CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
+    CTM_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
+    CTM_REQUIRE(a_imp || w_expect == 0.0, "w_expect needs an impurity tensor");
+    ctm::EnvOptions o = to_options(opts, d);
+    check_precision(o.precision);
+    CTM_REQUIRE(o.precision == CTM_PREC_F64, "gradients need precision CTM_PREC_F64");
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    ctm::Env env(ctx->c, d, chi, o);
+    const size_t d4 = (size_t)d * d * d * d;
+    {
+      ctm::DevBuf da(d4 * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      env.set_site_tensor_dev(da.d());
+      CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    }
+    env.init_boundary();
+    ctm::Grad g(env, sweeps, checkpoint_every);
+    g.forward();
+    double lk = 0.0, ex = 0.0;
+    g.seed(w_log_kappa, w_expect, nullptr, 0, a_imp, &lk, &ex);
+    g.backward();
+    g.grad_site(grad_a);
+    if (log_kappa) *log_kappa = lk;
+    if (expect) *expect = ex;
+    fill_info(g.stats, info);
+  });
 }
 
 int ctm_move(ctm_env* env, int direction) {

@@ -297,6 +297,11 @@ void Env::move(int k) {
   const double W = 2.0 * (5.0 * chi * chi * std::pow((double)d, 4) + 3.0 * std::pow((double)n, 3) +
                           8.0 * std::pow((double)chi, 3) * d * d + 6.0 * std::pow((double)chi, 3) * d);
   ScopedTimer tmove(ctx, 2, W);
+  const TapeLayout tl(chi, d);
+  if (tape_slot) {
+    copy_dev(ctx, tape_slot + tl.c, Call.d(), 4ull * chi * chi);
+    copy_dev(ctx, tape_slot + tl.t, Tall.d(), 4ull * chi * d * chi);
+  }
   for (int r = 0; r < 4; ++r)
     if (!qvalid[(k + r) & 3]) corner(k + r);
   const int q0 = k, q1 = (k + 1) & 3, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
@@ -311,6 +316,12 @@ void Env::move(int k) {
   svd_top(Mt.d(), k);
   const int kk = std::min(chi, b);
   inv_sqrt_cut(ctx, sv.d(), kk, chi, opt.eps_cut, winv.d());
+  if (tape_slot) {
+    copy_block(ctx, tape_slot + tl.ua, chi, UA.d(), b, n, kk);
+    copy_block(ctx, tape_slot + tl.va, chi, VA.d(), b, n, kk);
+    copy_dev(ctx, tape_slot + tl.s, sv.d(), kk);
+    copy_dev(ctx, tape_slot + tl.w, winv.d(), chi);
+  }
   if (kk < chi) {
     fill_zero(ctx, Pu.d(), (size_t)n * chi);
     fill_zero(ctx, Pl.d(), (size_t)n * chi);
@@ -349,9 +360,10 @@ void Env::move(int k) {
                      q3, 4 + q2);
   CTM_HIP(hipGetLastError());
   int* nflag = (int*)iflags.p;
-  normalise_maxabs(ctx, Cw(q0), (size_t)chi * chi, logs.d() + q0, nflag);
-  normalise_maxabs(ctx, Tw(q3), (size_t)chi * d * chi, logs.d() + 4 + q3, nflag);
-  normalise_maxabs(ctx, Cw(q3), (size_t)chi * chi, logs.d() + q3, nflag);
+  double* keep = tape_slot ? tape_slot + tl.inv : nullptr;
+  normalise_maxabs(ctx, Cw(q0), (size_t)chi * chi, logs.d() + q0, nflag, keep);
+  normalise_maxabs(ctx, Tw(q3), (size_t)chi * d * chi, logs.d() + 4 + q3, nflag, keep ? keep + 1 : nullptr);
+  normalise_maxabs(ctx, Cw(q3), (size_t)chi * chi, logs.d() + q3, nflag, keep ? keep + 2 : nullptr);
   qvalid[q0] = false;
   qvalid[q3] = false;
   e_valid = false;

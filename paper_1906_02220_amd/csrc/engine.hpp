@@ -15,7 +15,29 @@ struct EnvOptions {
   std::vector<double> boundary;  // empty: default
 };
 
+class Grad;
+
+// Per-move record of the forward pass kept for the adjoint: the environment
+// before the move, the kept singular triplets of the cut matrix and the
+// normalisation factors of the three renormalised tensors.
+struct TapeLayout {
+  size_t c, t, ua, va, s, w, inv, total;
+  TapeLayout(int chi, int d) {
+    const size_t n = (size_t)chi * d;
+    c = 0;
+    t = c + 4ull * chi * chi;
+    ua = t + 4ull * chi * d * chi;
+    va = ua + n * chi;
+    s = va + n * chi;
+    w = s + chi;
+    inv = w + chi;
+    total = inv + 4;
+  }
+};
+
 class Env {
+  friend class Grad;
+
  public:
   Env(Context& ctx, int d, int chi, const EnvOptions& opt);
   ~Env();
@@ -53,6 +75,8 @@ class Env {
   int sweeps_done = 0;
   EnvOptions opt;
   int b = 0;          // subspace size of the projector SVD
+  // When set, move() writes its TapeLayout record here (device memory).
+  double* tape_slot = nullptr;
 
  private:
   void alloc();

@@ -183,8 +183,13 @@ void permute(Context& ctx, const double* in, double* out, int rank, const long l
 void fill_zero(Context& ctx, double* p, size_t n);
 void fill_zero_int(Context& ctx, int* p, size_t n);
 void copy_dev(Context& ctx, double* dst, const double* src, size_t n);
+// dst[i * ldd + j] = src[i * lds + j] for i < rows, j < cols (row-major blocks).
+void copy_block(Context& ctx, double* dst, long long ldd, const double* src, long long lds,
+                int rows, int cols);
 // p /= max|p|; *log_slot += log(max|p|); *flag = 1 if p is not finite or all zero.
-void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag);
+// If inv_keep is not null, *inv_keep receives the factor 1/max|p| applied.
+void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag,
+                      double* inv_keep = nullptr);
 // *result = sum x[i] * y[i] (fixed-order two-stage reduction, deterministic)
 void dot(Context& ctx, const double* x, const double* y, size_t n, double* result);
 // Fill count doubles with standard normal numbers from the counter-based

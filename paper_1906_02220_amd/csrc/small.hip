@@ -65,6 +65,18 @@ __global__ void copy_kernel(double* __restrict__ d, const double* __restrict__ s
     d[i] = s[i];
 }
 
+__global__ void copy_block_kernel(double* __restrict__ dst, long long ldd,
+                                  const double* __restrict__ src, long long lds, int rows,
+                                  int cols) {
+  const long long total = (long long)rows * cols;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long i = idx / cols;
+    const long long j = idx - i * cols;
+    dst[i * ldd + j] = src[i * lds + j];
+  }
+}
+
 __global__ void fill_normal_kernel(double* p, size_t n, unsigned long long seed,
                                    unsigned long long ctr) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -112,19 +124,21 @@ __global__ void maxabs_partial_kernel(const double* __restrict__ p, size_t n, do
 }
 
 __global__ void maxabs_final_kernel(const double* partial, int nb, double* log_slot, int* flag,
-                                    double* inv_out) {
+                                    double* inv_out, double* inv_keep) {
   __shared__ double sh[256];
   double m = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, partial[i]);
   m = block_max256(m, sh);
   if (threadIdx.x == 0) {
+    double inv = 1.0;
     if (!(m < INFINITY) || m == 0.0) {
       *flag = 1;
-      *inv_out = 1.0;
     } else {
-      *inv_out = 1.0 / m;
+      inv = 1.0 / m;
       *log_slot += log(m);
     }
+    *inv_out = inv;
+    if (inv_keep) *inv_keep = inv;
   }
 }
 
@@ -620,6 +634,14 @@ void copy_dev(Context& ctx, double* dst, const double* src, size_t n) {
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, ctx.stream, dst, src, n);
   CTM_HIP(hipGetLastError());
 }
+void copy_block(Context& ctx, double* dst, long long ldd, const double* src, long long lds,
+                int rows, int cols) {
+  const size_t total = (size_t)rows * cols;
+  if (!total) return;
+  hipLaunchKernelGGL(copy_block_kernel, dim3(grid_for(total)), dim3(256), 0, ctx.stream, dst, ldd,
+                     src, lds, rows, cols);
+  CTM_HIP(hipGetLastError());
+}
 void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
                  unsigned long long counter) {
   if (!count) return;
@@ -628,13 +650,14 @@ void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
   CTM_HIP(hipGetLastError());
 }
 
-void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag) {
+void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag,
+                      double* inv_keep) {
   double* part = red_scratch(ctx);
   double* inv = part + kRedBlocks;
   const int nb = grid_for(n, 256, kRedBlocks);
   hipLaunchKernelGGL(maxabs_partial_kernel, dim3(nb), dim3(256), 0, ctx.stream, p, n, part);
   hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(256), 0, ctx.stream, part, nb, log_slot,
-                     flag, inv);
+                     flag, inv, inv_keep);
   hipLaunchKernelGGL(scale_by_dev_kernel, dim3(grid_for(n)), dim3(256), 0, ctx.stream, p, n, inv);
   CTM_HIP(hipGetLastError());
 }

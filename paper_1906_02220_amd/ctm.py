@@ -48,6 +48,17 @@ class ctm_opts(ctypes.Structure):
                 ("boundary", ctypes.POINTER(ctypes.c_double))]
 
 
+class ctm_grad_info(ctypes.Structure):
+    _fields_ = [("moves", ctypes.c_int),
+                ("cg_iters_max", ctypes.c_int),
+                ("cg_iters_total", ctypes.c_longlong),
+                ("ms_forward", ctypes.c_double),
+                ("ms_recompute", ctypes.c_double),
+                ("ms_backward", ctypes.c_double),
+                ("tape_bytes", ctypes.c_double),
+                ("checkpoint_bytes", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
@@ -83,6 +94,15 @@ SIGNATURES = {
     "ctm_env_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "ctm_env_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "ctm_env_dims": (ctypes.c_int, [_P, _I, _I, _I, _I]),
+    "ctm_grad_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(ctm_opts), ctypes.c_int,
+                                             ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_double, _D, _D, _D, _D,
+                                             ctypes.POINTER(ctm_grad_info)]),
+    "ctm_grad_tensor": (ctypes.c_int, [_P, _D, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctm_opts), ctypes.c_int, ctypes.c_int, _D,
+                                       ctypes.c_double, ctypes.c_double, _D, _D, _D,
+                                       ctypes.POINTER(ctm_grad_info)]),
     "ctm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_timing_reset": (ctypes.c_int, [_P]),
     "ctm_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _LL, _D, _D]),
@@ -207,6 +227,64 @@ def sweep_batch(envs, max_sweeps, tol=0.0):
                                         done.ctypes.data_as(_I), delta.ctypes.data_as(_D))
     envs[0].ctx.check(rc, "ctm_sweep_batch")
     return rc, done, delta
+
+
+def _info_dict(info):
+    return {name: getattr(info, name) for name, _ in ctm_grad_info._fields_}
+
+
+def grad_purification(ctx, A, B, gamma, chi, sweeps, op=None, w_log_kappa=1.0, w_expect=0.0,
+                      checkpoint_every=0, **kw):
+    """ctm_grad_purification: gradient of w_log_kappa ln(kappa) + w_expect <op>
+    after `sweeps` sweeps.  Returns (log_kappa, expect, dA, dB, info)."""
+    A = _f64(A)
+    B = _f64(B)
+    if A.shape != B.shape or A.ndim != 5 or A.shape[:2] != (2, 2):
+        raise ValueError("A and B must both have shape (2, 2, Dx, Dy, Dz)")
+    dims = list(A.shape[2:])
+    Dg = dims[gamma]
+    rest = [dims[i] for i in range(3) if i != gamma]
+    if rest[0] != rest[1]:
+        raise ValueError("the two non-fused bonds must share one dimension D")
+    o = default_opts(**kw)
+    opp, op_dim = None, 0
+    if op is not None:
+        opp = _f64(op)
+        op_dim = opp.shape[0]
+    gA = np.zeros_like(A)
+    gB = np.zeros_like(B)
+    lk = ctypes.c_double()
+    ex = ctypes.c_double()
+    info = ctm_grad_info()
+    rc = ctx.lib.ctm_grad_purification(ctx.h, _dptr(A), _dptr(B), rest[0], Dg, gamma, chi,
+                                       ctypes.byref(o), sweeps, checkpoint_every,
+                                       _dptr(opp) if opp is not None else None, op_dim,
+                                       w_log_kappa, w_expect, ctypes.byref(lk), ctypes.byref(ex),
+                                       _dptr(gA), _dptr(gB), ctypes.byref(info))
+    ctx.check(rc, "ctm_grad_purification")
+    return lk.value, ex.value, gA, gB, _info_dict(info)
+
+
+def grad_tensor(ctx, a, chi, sweeps, a_imp=None, w_log_kappa=1.0, w_expect=0.0,
+                checkpoint_every=0, **kw):
+    """ctm_grad_tensor: gradient of w_log_kappa ln(kappa) + w_expect <E,a_imp>/<E,a>
+    with respect to the site tensor a.  Returns (log_kappa, expect, da, info)."""
+    a = _f64(a)
+    d = a.shape[0]
+    if a.shape != (d, d, d, d):
+        raise ValueError("a must have shape (d, d, d, d)")
+    o = default_opts(**kw)
+    ai = _f64(a_imp) if a_imp is not None else None
+    ga = np.zeros_like(a)
+    lk = ctypes.c_double()
+    ex = ctypes.c_double()
+    info = ctm_grad_info()
+    rc = ctx.lib.ctm_grad_tensor(ctx.h, _dptr(a), d, chi, ctypes.byref(o), sweeps,
+                                 checkpoint_every, _dptr(ai) if ai is not None else None,
+                                 w_log_kappa, w_expect, ctypes.byref(lk), ctypes.byref(ex),
+                                 _dptr(ga), ctypes.byref(info))
+    ctx.check(rc, "ctm_grad_tensor")
+    return lk.value, ex.value, ga, _info_dict(info)
 
 
 class Environment:
