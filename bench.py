@@ -249,6 +249,45 @@ def run_batch(ctm, torch, synth, count, warm, steps):
     return out
 
 
+def run_grad(ctm, synth, reps):
+    """Reverse-mode gradient on the differentiation workload: D = 5, chi = 50
+    (n = 1250), seeds 5 (A, B) and 6 (bond operator), 30 fixed sweeps,
+    checkpoints every 5 sweeps, projector cutoff 5e-8, gradient of
+    ln kappa + <H_bond> with respect to A and B.  One untimed call, then
+    `reps` timed calls; also the plain forward (30 sweeps and both
+    observables) for the ratio."""
+    A, B = synth.random_purification(5, 5)
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    ctx = ctm.Context(0)
+    kw = dict(op=H, w_log_kappa=1.0, w_expect=1.0, checkpoint_every=5, eps_cut=5e-8)
+    ctm.grad_purification(ctx, A, B, 2, 50, 30, **kw)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lk, ex, gA, gB, info = ctm.grad_purification(ctx, A, B, 2, 50, 30, **kw)
+    dt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 50, eps_cut=5e-8)
+    env.sweep(30)
+    env.norm()
+    env.expect(H)
+    df = time.perf_counter() - t0
+    env.close()
+    ctx.close()
+    log("bench: gradient %.1f ms (forward alone %.1f ms)" % (1e3 * dt, 1e3 * df))
+    return {"workload": "d(ln kappa + <H_bond>)/d(A, B), D=5 chi=50 (n=1250), 30 sweeps, "
+                        "checkpoints every 5, eps_cut 5e-8, seeds 5/6, FP64",
+            "ms_per_gradient": round(1e3 * dt, 2), "ms_forward_only": round(1e3 * df, 2),
+            "gradient_over_forward": round(dt / df, 2),
+            "ms_first_forward": round(info["ms_forward"], 2),
+            "ms_recompute": round(info["ms_recompute"], 2),
+            "ms_reverse": round(info["ms_backward"], 2),
+            "cg_iters_per_move": round(info["cg_iters_total"] / max(info["moves"], 1), 2),
+            "cg_iters_max": info["cg_iters_max"],
+            "tape_MB": round(info["tape_bytes"] / 2 ** 20, 1),
+            "checkpoint_MB": round(info["checkpoint_bytes"] / 2 ** 20, 1),
+            "log_kappa": lk, "energy_bond": ex}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +300,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32,
                     help="environments of the batched-sweep measurement (0: skip it)")
+    ap.add_argument("--grad", type=int, default=3,
+                    help="timed calls of the gradient measurement (0: skip it)")
     ap.add_argument("--modes", default="0,1,3,4",
                     help="precision modes to time (0 FP64, 1 FP32, 3/4 BF16 slices); FP64 always runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -347,6 +388,8 @@ def main():
     }
     if args.batch > 0:
         out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
+    if args.grad > 0:
+        out["grad"] = run_grad(ctm, synth, args.grad)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(D, chi, seed)

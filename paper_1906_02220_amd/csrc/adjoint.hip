@@ -79,15 +79,18 @@ __global__ void axpby_kernel(double* y, const double* x, size_t n, double a, dou
 }
 
 // Y[i][j] = (acc ? Y[i][j] : 0) + X[i][j] * s_j^p, p = 1 or 2
-__global__ void col_scale_kernel(double* __restrict__ Y, const double* __restrict__ X, int rows,
-                                 int cols, const double* __restrict__ s, int p, int acc) {
+__global__ void col_scale_kernel(double* __restrict__ Y, long long ldy,
+                                 const double* __restrict__ X, long long ldx, int rows, int cols,
+                                 const double* __restrict__ s, int p, int acc) {
   const long long total = (long long)rows * cols;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(idx % cols);
+    const long long i = idx / cols;
+    const int j = (int)(idx - i * cols);
     const double f = p == 2 ? s[j] * s[j] : s[j];
-    const double v = X[idx] * f;
-    Y[idx] = acc ? Y[idx] + v : v;
+    const double v = X[i * ldx + j] * f;
+    double* y = Y + i * ldy + j;
+    *y = acc ? *y + v : v;
   }
 }
 
@@ -237,11 +240,16 @@ void axpby(Context& c, double* y, const double* x, size_t n, double a, double b)
   CTM_HIP(hipGetLastError());
 }
 
+void col_scale(Context& c, double* Y, long long ldy, const double* X, long long ldx, int rows,
+               int cols, const double* s, int p, bool acc) {
+  hipLaunchKernelGGL(col_scale_kernel, dim3(nblk((size_t)rows * cols)), dim3(256), 0, c.stream, Y,
+                     ldy, X, ldx, rows, cols, s, p, acc ? 1 : 0);
+  CTM_HIP(hipGetLastError());
+}
+
 void col_scale(Context& c, double* Y, const double* X, int rows, int cols, const double* s, int p,
                bool acc) {
-  hipLaunchKernelGGL(col_scale_kernel, dim3(nblk((size_t)rows * cols)), dim3(256), 0, c.stream, Y,
-                     X, rows, cols, s, p, acc ? 1 : 0);
-  CTM_HIP(hipGetLastError());
+  col_scale(c, Y, cols, X, cols, rows, cols, s, p, acc);
 }
 
 void coldot(Context& c, const double* X, const double* Y, int rows, int cols, double* out,
@@ -256,10 +264,14 @@ void scale_copy(Context& c, double* dst, const double* src, size_t n, const doub
   CTM_HIP(hipGetLastError());
 }
 
-// Z <- (1 - B B^T) Z for an n x chi block Z and orthonormal n x chi B.
-void project_out(Context& c, const double* B, double* Z, int n, int chi, double* tmp) {
-  mm(c, chi, chi, n, B, chi, true, Z, chi, false, tmp, chi);
-  mm(c, n, chi, chi, B, chi, false, tmp, chi, false, Z, chi, 1.0, -1.0);
+// Z_z <- (1 - B_z B_z^T) Z_z for two n x chi blocks Z_z and orthonormal
+// n x chi B_z, z = 0, 1, each pair stored nc = n chi apart.
+void project_out2(Context& c, const double* B, double* Z, int n, int chi, double* tmp) {
+  const long long nc = (long long)n * chi, cc = (long long)chi * chi;
+  gemm_f64(c, chi, chi, n, 1.0, colmajor(B, chi, nc), rowmajor(Z, chi, nc), 0.0,
+           out_rowmajor(tmp, chi, cc), 2);
+  gemm_f64(c, n, chi, chi, -1.0, rowmajor(B, chi, nc), rowmajor(tmp, chi, cc), 1.0,
+           out_rowmajor(Z, chi, nc), 2);
 }
 
 double now_ms() {
@@ -289,13 +301,20 @@ Grad::Grad(Env& env, int sweeps_, int ckpt_every)
   Tb.alloc(4 * ct * sizeof(double));
   for (auto& x : arb) x.alloc(dd4 * sizeof(double));
   abar.alloc(dd4 * sizeof(double));
-  for (DevBuf* x : {&Ubar, &Ltbar, &Mtbar, &Qbar, &wA, &wB}) x->alloc(big * sizeof(double));
+  for (DevBuf* x : {&Qbar, &wA, &wB}) x->alloc(big * sizeof(double));
+  Mt3.alloc(3ull * n * n * sizeof(double));
   for (DevBuf* x : {&PuU, &PlU, &Pub, &Plb, &UAw, &VAw, &UAb, &VAb, &x1e, &G1T, &G2, &pb, &sm1b, &X1b})
     x->alloc(nc * sizeof(double));
-  for (int s = 0; s < 2; ++s)
-    for (DevBuf* x : {&cgX[s], &cgR[s], &cgP[s], &cgAP[s], &cgXb[s], &cgT[s]})
-      x->alloc(nc * sizeof(double));
-  for (DevBuf* x : {&ckb, &cq3b, &Gu, &Gv, &Zm, &tmpA, &tmpB}) x->alloc(cc * sizeof(double));
+  for (DevBuf* x : {&LU, &RU, &LL, &RL, &Wf}) x->alloc(2 * nc * sizeof(double));
+  for (DevBuf* x : {&cgX, &cgR, &cgP, &cgAP, &cgXb, &cgT}) x->alloc(2 * nc * sizeof(double));
+  for (DevBuf* x : {&ckb, &cq3b, &Gu, &Gv, &Zm, &tmpB}) x->alloc(cc * sizeof(double));
+  tmpA.alloc(2 * cc * sizeof(double));
+  for (int f = 0; f < 4; ++f) {
+    arotT[f].alloc(dd4 * sizeof(double));
+    const long long dd2[2] = {(long long)d * d, (long long)d * d};
+    const int p10[2] = {1, 0};
+    permute(ctx, e.arot[f].d(), arotT[f].d(), 2, dd2, p10);
+  }
   tq3b.alloc(ct * sizeof(double));
   sm2b.alloc(ct * sizeof(double));
   wbar.alloc(chi * sizeof(double));
@@ -399,9 +418,11 @@ double Grad::seed(double wk, double wo, const double* op, int op_dim, const doub
   double* u2 = PlU.d();   // (C1 T1) C2   [a,u][e]
   double* l1 = Pub.d();   // C3 T3        [h][x,c]
   double* l2 = Plb.d();   // (C3 T3) C4   [h,x][d']
-  double* Uh = Ubar.d();  // [u,r][a,h]
-  double* Lh = Ltbar.d(); // [a,h][x,l]
-  double* E = Mtbar.d();  // [u,l,x,r]
+  DevBuf sUh((size_t)d2 * c2 * sizeof(double)), sLh((size_t)d2 * c2 * sizeof(double)),
+      sE(d4 * sizeof(double));
+  double* Uh = sUh.d();  // [u,r][a,h]
+  double* Lh = sLh.d();  // [a,h][x,l]
+  double* E = sE.d();    // [u,l,x,r]
   const long long d4c[4] = {chi, d, d, chi};
   mm(ctx, chi, dc, chi, C[0], chi, false, T[0], dc, false, u1, dc);
   mm(ctx, dc, chi, chi, u1, chi, false, C[1], chi, false, u2, chi);
@@ -595,26 +616,26 @@ double Grad::seed(double wk, double wo, const double* op, int op_dim, const doub
   return wk * lk + wo * ex;
 }
 
-// Complement solves of the SVD adjoint, both systems at once: returns the
-// number of iterations.  Right-hand sides in UAb, VAb; solutions in cgXb.
-int Grad::cg(const double* UA, const double* VA, const double* s) {
-  const double* Mt = e.Mt.d();
-  const size_t nc = (size_t)n * chi;
-  const double* basis[2] = {UA, VA};
-  for (int sy = 0; sy < 2; ++sy) {
-    double* R = cgR[sy].d();
-    copy_dev(ctx, R, sy ? VAb.d() : UAb.d(), nc);
-    project_out(ctx, basis[sy], R, n, chi, tmpA.d());
-    project_out(ctx, basis[sy], R, n, chi, tmpA.d());
-    copy_dev(ctx, cgP[sy].d(), R, nc);
-  }
+// Complement solves of the SVD adjoint, both systems at once (system 0 on
+// the left vectors with Mt Mt^T, system 1 on the right vectors with
+// Mt^T Mt; VA = UA + n chi in the tape): returns the number of iterations.
+// Right-hand sides in UAb, VAb; solutions in cgXb (then cgXb + n chi).
+int Grad::cg(const double* UA, const double* s) {
+  const size_t nc = (size_t)n * chi, nn = (size_t)n * n;
+  const double* MtT = Mt3.d();  // [Mt^T | Mt | Mt^T]
+  double* R = cgR.d();
+  copy_dev(ctx, R, UAb.d(), nc);
+  copy_dev(ctx, R + nc, VAb.d(), nc);
+  project_out2(ctx, UA, R, n, chi, tmpA.d());
+  project_out2(ctx, UA, R, n, chi, tmpA.d());
+  copy_dev(ctx, cgP.d(), R, 2 * nc);
   CgArgs a;
   for (int sy = 0; sy < 2; ++sy) {
-    a.X[sy] = cgX[sy].d();
-    a.R[sy] = cgR[sy].d();
-    a.P[sy] = cgP[sy].d();
-    a.AP[sy] = cgAP[sy].d();
-    a.Xb[sy] = cgXb[sy].d();
+    a.X[sy] = cgX.d() + sy * nc;
+    a.R[sy] = cgR.d() + sy * nc;
+    a.P[sy] = cgP.d() + sy * nc;
+    a.AP[sy] = cgAP.d() + sy * nc;
+    a.Xb[sy] = cgXb.d() + sy * nc;
   }
   a.rr = rr.d();
   a.bn = bn.d();
@@ -627,20 +648,20 @@ int Grad::cg(const double* UA, const double* VA, const double* s) {
   a.tol = 1e-13;
   hipLaunchKernelGGL(cg_init_kernel, dim3(2 * chi), dim3(256), 0, ctx.stream, a);
   CTM_HIP(hipGetLastError());
+  double* P = cgP.d();
+  double* AP = cgAP.d();
+  double* T1 = cgT.d();
   const int maxit = 300;
   int it = 0;
   for (it = 1; it <= maxit; ++it) {
-    for (int sy = 0; sy < 2; ++sy) {
-      double* P = cgP[sy].d();
-      double* AP = cgAP[sy].d();
-      double* T1 = cgT[sy].d();
-      project_out(ctx, basis[sy], P, n, chi, tmpA.d());
-      // AP = s^2 P - G P, G = Mt Mt^T (sy 0) or Mt^T Mt (sy 1)
-      mm(ctx, n, chi, n, Mt, n, sy == 0, P, chi, false, T1, chi);
-      col_scale(ctx, AP, P, n, chi, s, 2, false);
-      mm(ctx, n, chi, n, Mt, n, sy == 1, T1, chi, false, AP, chi, 1.0, -1.0);
-      project_out(ctx, basis[sy], AP, n, chi, tmpA.d());
-    }
+    project_out2(ctx, UA, P, n, chi, tmpA.d());
+    // AP = s^2 P - G P:  T1 = (Mt^T | Mt) P,  AP -= (Mt | Mt^T) T1
+    gemm_f64(ctx, n, chi, n, 1.0, rowmajor(MtT, n, nn), rowmajor(P, chi, nc), 0.0,
+             out_rowmajor(T1, chi, nc), 2);
+    col_scale(ctx, AP, P, 2 * n, chi, s, 2, false);
+    gemm_f64(ctx, n, chi, n, -1.0, rowmajor(MtT + nn, n, nn), rowmajor(T1, chi, nc), 1.0,
+             out_rowmajor(AP, chi, nc), 2);
+    project_out2(ctx, UA, AP, n, chi, tmpA.d());
     fill_zero_int(ctx, (int*)count.p, 1);
     hipLaunchKernelGGL(cg_step_kernel, dim3(2 * chi), dim3(256), 0, ctx.stream, a);
     CTM_HIP(hipGetLastError());
@@ -653,35 +674,35 @@ int Grad::cg(const double* UA, const double* VA, const double* s) {
   return std::min(it, maxit);
 }
 
-// Adjoint of the truncated SVD: Mtbar (n x n) from UAb, VAb, the singular
-// values s and w = s^-1/2 (wbar already holds the adjoint of w).
+// Adjoint of the truncated SVD in factored form: from UAb, VAb, the
+// singular values s and w = s^-1/2 (wbar holds the adjoint of w),
+//   Mt_bar = UA G1 + G2 VA^T,  G1^T = Mt^T Xc + Yc S + VA Z^T,  G2 = Mt Yc + Xc S.
 void Grad::svd_bwd(const double* UA, const double* VA, const double* s, const double* w) {
-  const double* Mt = e.Mt.d();
+  const size_t nc = (size_t)n * chi, nn = (size_t)n * n;
+  const double* MtT = Mt3.d();
+  const double* Mt = Mt3.d() + nn;
   mm(ctx, chi, chi, n, UA, chi, true, UAb.d(), chi, false, Gu.d(), chi);
   mm(ctx, chi, chi, n, VA, chi, true, VAb.d(), chi, false, Gv.d(), chi);
   hipLaunchKernelGGL(svd_core_kernel, dim3(1), dim3(256), 0, ctx.stream, Gu.d(), Gv.d(), s, w,
                      wbar.d(), chi, 1e-12, Zm.d(), sbar.d());
   CTM_HIP(hipGetLastError());
-  const int its = cg(UA, VA, s);
+  const int its = cg(UA, s);
   stats.cg_iters_max = std::max(stats.cg_iters_max, its);
   stats.cg_iters_total += its;
-  const double* Xc = cgXb[0].d();
-  const double* Yc = cgXb[1].d();
-  // G1^T = Mt^T Xc + Yc S + VA Z^T;  G2 = Mt Yc + Xc S
-  mm(ctx, n, chi, n, Mt, n, true, Xc, chi, false, G1T.d(), chi);
+  const double* Xc = cgXb.d();
+  const double* Yc = cgXb.d() + nc;
+  mm(ctx, n, chi, n, MtT, n, false, Xc, chi, false, G1T.d(), chi);
   col_scale(ctx, G1T.d(), Yc, n, chi, s, 1, true);
   mm(ctx, n, chi, chi, VA, chi, false, Zm.d(), chi, true, G1T.d(), chi, 1.0);
   mm(ctx, n, chi, n, Mt, n, false, Yc, chi, false, G2.d(), chi);
   col_scale(ctx, G2.d(), Xc, n, chi, s, 1, true);
-  // Mtbar = UA G1 + G2 VA^T
-  mm(ctx, n, n, chi, UA, chi, false, G1T.d(), chi, true, Mtbar.d(), n);
-  mm(ctx, n, n, chi, G2.d(), chi, false, VA, chi, true, Mtbar.d(), n, 1.0);
 }
 
 void Grad::move_bwd(int k, const double* rec) {
   const int dc = d * chi;
   const long long d2 = (long long)d * d, c2 = (long long)chi * chi;
   const size_t cc = (size_t)chi * chi, ct = (size_t)chi * d * chi, nc = (size_t)n * chi;
+  const size_t nn = (size_t)n * n;
   const int q0 = k, q1 = (k + 1) & 3, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
   const double* UA = rec + tl.ua;
   const double* VA = rec + tl.va;
@@ -706,15 +727,19 @@ void Grad::move_bwd(int k, const double* rec) {
   fill_zero(ctx, Cbar[q0], cc);
   fill_zero(ctx, Tbar[q3], ct);
   fill_zero(ctx, Cbar[q3], cc);
-  // corners, halves, cut matrix, projectors
+  // corners, halves, cut matrix (and its transpose, twice), projectors
   for (int f = 0; f < 4; ++f) e.corner(f);
   const double* Q[4] = {e.Qb[0].d(), e.Qb[1].d(), e.Qb[2].d(), e.Qb[3].d()};
   double* U = e.U.d();
   double* Lt = e.Lt.d();
-  double* Mt = e.Mt.d();
+  double* Mt = Mt3.d() + nn;
   mm(ctx, n, n, n, Q[q0], n, false, Q[q1], n, false, U, n);
   mm(ctx, n, n, n, Q[q2], n, false, Q[q3], n, false, Lt, n);
   mm(ctx, n, n, n, Lt, n, false, U, n, false, Mt, n);
+  const long long nd[2] = {n, n};
+  const int p10[2] = {1, 0};
+  permute(ctx, Mt, Mt3.d(), 2, nd, p10);
+  copy_dev(ctx, Mt3.d() + 2 * nn, Mt3.d(), nn);
   mm(ctx, n, chi, n, Lt, n, true, UA, chi, false, PuU.d(), chi);
   mm(ctx, n, chi, n, U, n, false, VA, chi, false, PlU.d(), chi);
   double* Pu = e.Pu.d();
@@ -727,20 +752,24 @@ void Grad::move_bwd(int k, const double* rec) {
   permute(ctx, tq3b.d(), sm2b.d(), 3, e3, p021);  // [k1][k2][r]
   const long long d4c[4] = {chi, d, d, chi};
   const int p0321[4] = {0, 3, 2, 1};
+  const int p2103[4] = {2, 1, 0, 3};
   const long long e4[4] = {chi, chi, d, d};
   const long long e4b[4] = {chi, d, chi, d};
   const int p0213[4] = {0, 2, 1, 3};
   double* t2 = e.t2.d();
+  double* t2T = e.t1.d();
   const double* ar = e.arot[q0].d();
   mm(ctx, dc, dc, chi, T[q3], chi, false, Pl, dc, false, wA.d(), dc);  // [de,l][u,k2]
   permute(ctx, wA.d(), t2, 4, d4c, p0321);                              // [de,k2][u,l]
+  permute(ctx, wA.d(), t2T, 4, d4c, p2103);                             // [u,l][de,k2]
   mm(ctx, c2, d2, d2, t2, d2, false, ar, d2, false, wA.d(), d2);          // [de,k2][dd,r]
   permute(ctx, wA.d(), wB.d(), 4, e4, p0213);                           // [de,dd][k2,r]
   mm(ctx, n, chi, dc, wB.d(), dc, false, sm2b.d(), dc, true, Pub.d(), chi);
   mm(ctx, n, dc, chi, Pu, chi, false, sm2b.d(), dc, false, wA.d(), dc);   // t2b_bar
   permute(ctx, wA.d(), wB.d(), 4, e4b, p0213);                          // [de,k2][dd,r]
-  mm(ctx, d2, d2, c2, t2, d2, true, wB.d(), d2, false, arb[q0].d(), d2, 1.0);
-  mm(ctx, c2, d2, d2, wB.d(), d2, false, ar, d2, true, wA.d(), d2);      // t2_bar
+  mm(ctx, d2, d2, c2, t2T, c2, false, wB.d(), d2, false, Qbar.d(), d2);
+  axpby(ctx, arb[q0].d(), Qbar.d(), (size_t)d2 * d2, 1.0, 1.0);
+  mm(ctx, c2, d2, d2, wB.d(), d2, false, arotT[q0].d(), d2, false, wA.d(), d2);  // t2_bar
   permute(ctx, wA.d(), wB.d(), 4, e4, p0321);                           // t1_bar [de,l][u,k2]
   mm(ctx, dc, chi, dc, wB.d(), dc, false, Pl, dc, true, Tbar[q3], chi, 1.0);
   mm(ctx, chi, dc, dc, T[q3], chi, true, wB.d(), dc, false, Plb.d(), dc);
@@ -758,36 +787,56 @@ void Grad::move_bwd(int k, const double* rec) {
   const double* X1 = e.X1[q0].d();
   mm(ctx, n, chi, chi, X1, chi, false, ckb.d(), chi, true, Pub.d(), chi, 1.0);
   mm(ctx, n, chi, chi, Pu, chi, false, ckb.d(), chi, false, x1e.d(), chi);
-  // projectors: Pu = Lt^T UA w, Pl = U VA w
-  col_scale(ctx, UAw.d(), UA, n, chi, w, 1, false);
-  col_scale(ctx, VAw.d(), VA, n, chi, w, 1, false);
-  mm(ctx, n, n, chi, UAw.d(), chi, false, Pub.d(), chi, true, Ltbar.d(), n);
+  // projectors Pu = Lt^T UA w, Pl = U VA w: adjoints of UA, VA and w
   mm(ctx, n, chi, n, Lt, n, false, Pub.d(), chi, false, UAb.d(), chi);
   scale_cols(ctx, UAb.d(), n, chi, chi, w);
   coldot(ctx, Pub.d(), PuU.d(), n, chi, wbar.d(), false);
-  mm(ctx, n, n, chi, Plb.d(), chi, false, VAw.d(), chi, true, Ubar.d(), n);
   mm(ctx, n, chi, n, U, n, true, Plb.d(), chi, false, VAb.d(), chi);
   scale_cols(ctx, VAb.d(), n, chi, chi, w);
   coldot(ctx, Plb.d(), PlU.d(), n, chi, wbar.d(), true);
-  // cut matrix
+  // cut matrix: Mt_bar = UA G1 + G2 VA^T
   svd_bwd(UA, VA, s, w);
-  mm(ctx, n, n, n, Mtbar.d(), n, false, U, n, true, Ltbar.d(), n, 1.0);
-  mm(ctx, n, n, n, Lt, n, true, Mtbar.d(), n, false, Ubar.d(), n, 1.0);
-  // enlarged corners
+  // Halves in factored form (rank 2 chi):
+  //   U_bar  = Pl_bar w VA^T + Lt^T Mt_bar = [Pl_bar w + Lt^T G2 | Lt^T UA] [VA | G1^T]^T
+  //   Lt_bar = UA w Pu_bar^T + Mt_bar U^T  = [UA | G2] [Pu_bar w + U G1^T | U VA]^T
+  const int c2x = 2 * chi;
+  col_scale(ctx, LU.d(), c2x, Plb.d(), chi, n, chi, w, 1, false);
+  gemm_f64(ctx, n, chi, n, 1.0, colmajor(Lt, n), rowmajor(G2.d(), chi), 1.0,
+           out_rowmajor(LU.d(), c2x));
+  copy_block(ctx, LU.d() + chi, c2x, PuU.d(), chi, n, chi);
+  copy_block(ctx, RU.d(), c2x, VA, chi, n, chi);
+  copy_block(ctx, RU.d() + chi, c2x, G1T.d(), chi, n, chi);
+  copy_block(ctx, LL.d(), c2x, UA, chi, n, chi);
+  copy_block(ctx, LL.d() + chi, c2x, G2.d(), chi, n, chi);
+  col_scale(ctx, RL.d(), c2x, Pub.d(), chi, n, chi, w, 1, false);
+  gemm_f64(ctx, n, chi, n, 1.0, rowmajor(U, n), rowmajor(G1T.d(), chi), 1.0,
+           out_rowmajor(RL.d(), c2x));
+  copy_block(ctx, RL.d() + chi, c2x, PlU.d(), chi, n, chi);
+  // enlarged corners: Q_bar of each, then its adjoint
   for (int r = 0; r < 4; ++r) {
     const int f = (k + r) & 3;
     double* Qb = Qbar.d();
-    if (r == 0) mm(ctx, n, n, n, Ubar.d(), n, false, Q[q1], n, true, Qb, n);
-    if (r == 1) mm(ctx, n, n, n, Q[q0], n, true, Ubar.d(), n, false, Qb, n);
-    if (r == 2) mm(ctx, n, n, n, Ltbar.d(), n, false, Q[q3], n, true, Qb, n);
-    if (r == 3) mm(ctx, n, n, n, Q[q2], n, true, Ltbar.d(), n, false, Qb, n);
+    if (r == 0) {  // U_bar Q1^T = LU (Q1 RU)^T
+      mm(ctx, n, c2x, n, Q[q1], n, false, RU.d(), c2x, false, Wf.d(), c2x);
+      mm(ctx, n, n, c2x, LU.d(), c2x, false, Wf.d(), c2x, true, Qb, n);
+    } else if (r == 1) {  // Q0^T U_bar = (Q0^T LU) RU^T
+      mm(ctx, n, c2x, n, Q[q0], n, true, LU.d(), c2x, false, Wf.d(), c2x);
+      mm(ctx, n, n, c2x, Wf.d(), c2x, false, RU.d(), c2x, true, Qb, n);
+    } else if (r == 2) {  // Lt_bar Q3^T = LL (Q3 RL)^T
+      mm(ctx, n, c2x, n, Q[q3], n, false, RL.d(), c2x, false, Wf.d(), c2x);
+      mm(ctx, n, n, c2x, LL.d(), c2x, false, Wf.d(), c2x, true, Qb, n);
+    } else {  // Q2^T Lt_bar = (Q2^T LL) RL^T
+      mm(ctx, n, c2x, n, Q[q2], n, true, LL.d(), c2x, false, Wf.d(), c2x);
+      mm(ctx, n, n, c2x, Wf.d(), c2x, false, RL.d(), c2x, true, Qb, n);
+    }
     const int g = (f + 3) & 3;
     const double* Xf = e.X1[f].d();
     permute(ctx, Qb, wA.d(), 4, e4b, p0213);  // [de,ga][dd,r]
     mm(ctx, dc, dc, chi, T[g], chi, false, Xf, dc, false, wB.d(), dc);
-    permute(ctx, wB.d(), t2, 4, d4c, p0321);  // [de,ga][u,l]
-    mm(ctx, d2, d2, c2, t2, d2, true, wA.d(), d2, false, arb[f].d(), d2, 1.0);
-    mm(ctx, c2, d2, d2, wA.d(), d2, false, e.arot[f].d(), d2, true, wB.d(), d2);
+    permute(ctx, wB.d(), t2T, 4, d4c, p2103);  // [u,l][de,ga]
+    mm(ctx, d2, d2, c2, t2T, c2, false, wA.d(), d2, false, Qb, d2);
+    axpby(ctx, arb[f].d(), Qb, (size_t)d2 * d2, 1.0, 1.0);
+    mm(ctx, c2, d2, d2, wA.d(), d2, false, arotT[f].d(), d2, false, wB.d(), d2);
     permute(ctx, wB.d(), wA.d(), 4, e4, p0321);  // t1_bar [de,l][u,ga]
     mm(ctx, dc, chi, dc, wA.d(), dc, false, Xf, dc, true, Tbar[g], chi, 1.0);
     mm(ctx, chi, dc, dc, T[g], chi, true, wA.d(), dc, false, X1b.d(), dc);

@@ -45,7 +45,7 @@ class Grad {
   void run_segment(int sg, bool record);
   void move_bwd(int k, const double* rec);
   void svd_bwd(const double* UA, const double* VA, const double* s, const double* w);
-  int cg(const double* UA, const double* VA, const double* s);
+  int cg(const double* UA, const double* s);
   void site_total();
 
   Env& e;
@@ -57,11 +57,13 @@ class Grad {
   DevBuf tape;
   // adjoints
   DevBuf Cb, Tb, arb[4], abar, Kcb;
-  // n^2 (or d^4) work
-  DevBuf Ubar, Ltbar, Mtbar, Qbar, wA, wB;
-  // n x chi work
+  // n^2 (or d^4) work; [Mt^T | Mt | Mt^T]; transposed rotated site tensors
+  DevBuf Qbar, wA, wB, Mt3, arotT[4];
+  // n x chi work, n x 2 chi factors of the half-system adjoints
   DevBuf PuU, PlU, Pub, Plb, UAw, VAw, UAb, VAb, x1e, G1T, G2, pb, sm1b, X1b;
-  DevBuf cgX[2], cgR[2], cgP[2], cgAP[2], cgXb[2], cgT[2];
+  DevBuf LU, RU, LL, RL, Wf;
+  // conjugate gradients: both systems stacked (n chi apart)
+  DevBuf cgX, cgR, cgP, cgAP, cgXb, cgT;
   // chi x chi and smaller
   DevBuf ckb, cq3b, tq3b, sm2b, Gu, Gv, Zm, tmpA, tmpB, wbar, sbar;
   DevBuf rr, bn, best, stall, active, count;

@@ -5,6 +5,11 @@ arguments (numpy arrays for host buffers); the classes ``Context`` and
 ``Environment`` wrap them for convenience.  All computation happens in the
 HIP library; if ``libctm.so`` is missing or cannot be loaded, importing the
 library raises instead of falling back to anything else.
+
+When torch is used in the same process, import torch before the library is
+first loaded: torch ships its own HIP runtime, and loading it first makes the
+library bind to that one instead of starting a second runtime beside it (with
+which torch would then find no device).
 """
 import ctypes
 import os

@@ -7,6 +7,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# torch ships its own HIP runtime.  Loading it before libctm.so lets the
+# library bind to that same runtime; the other order leaves two runtimes in
+# the process and torch then finds no device.  (Importing is enough; it does
+# not touch the GPU.)
+try:
+    import torch  # noqa: F401
+except Exception:
+    pass
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

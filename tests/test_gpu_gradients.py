@@ -207,3 +207,27 @@ def test_gradient_argument_errors(ctx):
     lk, ex, gA, gB, info = ctm.grad_purification(ctx, A, B, 2, 8, 0, op=H)
     assert info["moves"] == 0 and np.isfinite(lk)
     assert abs(np.sum(gA * A) - 2.0) < 1e-12
+
+
+def test_torch_autograd_function(ctx):
+    """The torch.autograd binding returns the library's value and propagates
+    its gradient through further torch arithmetic."""
+    import torch
+    from paper_1906_02220_amd import autograd as AG
+    say("case: torch.autograd binding D=2 chi=4")
+    A, B = synth.random_purification(2, 7)
+    At = torch.tensor(A, device="cuda", requires_grad=True)
+    Bt = torch.tensor(B, device="cuda", requires_grad=True)
+    L = AG.purification_objective(ctx, At, Bt, 2, 4, 10, op=H, w_log_kappa=1.0, w_expect=0.5)
+    (3.0 * L + L * L).backward()
+    lk, ex, gA, gB, _ = ctm.grad_purification(ctx, A, B, 2, 4, 10, op=H, w_log_kappa=1.0,
+                                              w_expect=0.5)
+    assert abs(L.item() - (lk + 0.5 * ex)) < 1e-14
+    f = 3.0 + 2.0 * L.item()
+    assert np.allclose(At.grad.cpu().numpy(), f * gA, rtol=1e-13, atol=0)
+    assert np.allclose(Bt.grad.cpu().numpy(), f * gB, rtol=1e-13, atol=0)
+    a = torch.tensor(synth.ising_square_tensor(0.4), requires_grad=True)
+    La = AG.tensor_objective(ctx, a, 8, 10)
+    La.backward()
+    lk, ex, ga, _ = ctm.grad_tensor(ctx, synth.ising_square_tensor(0.4), 8, 10)
+    assert np.array_equal(a.grad.numpy(), ga)
