@@ -16,6 +16,8 @@ closed_forms  independent closed forms used to pin the oracle (Onsager,
 brute         exact contraction of small finite lattices by a row transfer
               matrix (no truncation), used to pin the move semantics.
 gates         two-site gate and its rank-4 split, used to build test inputs.
+fu            one full-update bond truncation: gate, environment of the
+              gated composite, alternating least squares in its metric.
 gradients     directional derivatives of the oracle's objectives (ln kappa,
               <O>) by fourth-order central differences: the reference for
               the hand-written adjoint of the HIP path.
