@@ -115,3 +115,18 @@ def bond_update(A, B, gamma, H, tau, chi, sweeps, als_iters, eps_cut=O.EPS_CUT_D
     Ap, Bp, errs = truncate(to_fused(Ag, gamma), to_fused(Bg, gamma), E8,
                            to_fused(A, gamma), to_fused(B, gamma), als_iters)
     return from_fused(Ap, gamma), from_fused(Bp, gamma), errs, E8
+
+
+TROTTER = ((0, 0.5), (1, 0.5), (2, 1.0), (1, 0.5), (0, 0.5))  # (gamma, fraction of dbeta)
+
+
+def trotter_step(A, B, H3, dbeta, chi, sweeps, als_iters, eps_cut=O.EPS_CUT_DEFAULT):
+    """Second-order Trotter step (Sec. III): G_x(db/2) G_y(db/2) G_z(db)
+    G_y(db/2) G_x(db/2) applied right to left, G_gamma(t) the bond update
+    with the gate exp(-t H_gamma / 2).  Returns (A, B, error histories)."""
+    hist = []
+    for gamma, frac in TROTTER:
+        A, B, errs, _ = bond_update(A, B, gamma, H3[gamma], frac * dbeta, chi, sweeps, als_iters,
+                                    eps_cut)
+        hist.append(errs)
+    return A, B, hist

@@ -52,3 +52,16 @@ def test_als_rounds_never_raise_the_error():
     Es = 0.5 * (E + E.T)
     assert np.abs(E - E.T).max() < 1e-6 * np.abs(E).max()
     assert np.linalg.eigvalsh(Es).min() > -1e-8 * np.abs(Es).max()
+
+
+def test_trotter_step_with_only_z_bonds_is_one_z_update():
+    """H_x = H_y = 0: the four x and y gates are the identity, so the step is
+    the z-bond update with tau = dbeta (Sec. III gate sequence)."""
+    D = 2
+    A, B = synth.random_purification(D, 9)
+    Hz = synth.bond_operator_real(synth.random_coefficients(10))
+    Z = np.zeros((4, 4))
+    A1, B1, _ = fu.trotter_step(A, B, [Z, Z, Hz], 0.3, 8, 5, 3)
+    A2, B2, _, _ = fu.bond_update(A, B, 2, Hz, 0.3, 8, 5, 3)
+    K1, K2 = O.composite(A1, B1, 2), O.composite(A2, B2, 2)
+    assert np.abs(K1 - K2).max() < 1e-9 * np.abs(K2).max()
