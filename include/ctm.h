@@ -254,6 +254,37 @@ int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm
                     double w_expect, double* log_kappa, double* expect, double* grad_a,
                     ctm_grad_info* info);
 
+/* One bond update of the exact-environment full update (Sec. III,
+ * Fig. 3(b), Fig. 4).  The gate exp(-tau H/2) of the real 4 x 4 bond term H
+ * (row-major, index (s_A s_B)(s_A' s_B'), acting on the pseudospins) is
+ * split by SVD into two gate tensors joined by an index of dimension 4 and
+ * contracted with A and B, so that the gamma bond grows to 4D.  The
+ * environment of the gated composite A'-B' (the 4D bond hidden inside it)
+ * comes from `sweeps` CTMRG sweeps at chi with opts, as the bond metric E of
+ * the composite's outer legs.  Then `als_iters` rounds of alternating least
+ * squares (A'' with B'' fixed, then B'' with A'' fixed, from A'' = A,
+ * B'' = B) minimise the error of the purification in that metric,
+ *   d = sum_p <K'_p - K''_p, E (K'_p - K''_p)>,  K = composite over gamma,
+ * with E symmetrised and a ridge of 1e-12 tr(N)/dim(N) on each normal
+ * matrix.  A, B, A_out, B_out: host [2][2][D][D][D], every bond D <= 8;
+ * errors (host, als_iters + 1 entries, may be null): d / <K', E K'> at the
+ * start and after each round.  CTM_ENUMERIC if a sweep fails or a normal
+ * matrix is not positive definite. */
+int ctm_fu_bond_update(ctm_context* ctx, const double* A, const double* B, int D, int gamma,
+                       const double* H, double tau, int chi, const ctm_opts* opts, int sweeps,
+                       int als_iters, double* A_out, double* B_out, double* errors);
+
+/* One second-order Trotter step of the imaginary-time evolution (Sec. III):
+ * the bond updates G_x(dbeta/2) G_y(dbeta/2) G_z(dbeta) G_y(dbeta/2)
+ * G_x(dbeta/2), applied right to left, where G_gamma(t) uses the gate
+ * exp(-t H_gamma / 2) on every gamma bond.  H: three 4 x 4 bond terms
+ * (x, y, z) one after the other.  A and B (host [2][2][D][D][D]) are
+ * updated in place.  errors (host, 5 (als_iters + 1) entries, may be null):
+ * the error history of each of the five bond updates. */
+int ctm_fu_trotter_step(ctm_context* ctx, double* A, double* B, int D, const double* H,
+                        double dbeta, int chi, const ctm_opts* opts, int sweeps, int als_iters,
+                        double* errors);
+
 /* Kernel timing over the calls since the last reset, measured with HIP
  * events on the context's stream around every launch of one kernel class.
  * cls 0: FP64 GEMMs of the n x n x n half-system and cut products;

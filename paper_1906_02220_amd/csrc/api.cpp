@@ -12,6 +12,7 @@
 
 #include "ctm.h"
 #include "adjoint.hpp"
+#include "fu.hpp"
 #include "engine.hpp"
 
 // The context state is shared by the context handle and every environment
@@ -413,6 +414,51 @@ int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm
     if (log_kappa) *log_kappa = lk;
     if (expect) *expect = ex;
     fill_info(g.stats, info);
+  });
+}
+
+int ctm_fu_bond_update(ctm_context* ctx, const double* A, const double* B, int D, int gamma,
+                       const double* H, double tau, int chi, const ctm_opts* opts, int sweeps,
+                       int als_iters, double* A_out, double* B_out, double* errors) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(A && B && H && A_out && B_out, "null argument");
+    CTM_REQUIRE(D >= 1 && D <= 8, "D must be 1..8");
+    CTM_REQUIRE(gamma >= 0 && gamma <= 2, "gamma must be 0, 1 or 2");
+    CTM_REQUIRE(chi >= 1 && sweeps >= 0 && als_iters >= 0, "chi >= 1, sweeps and als_iters >= 0");
+    CTM_REQUIRE(std::isfinite(tau), "tau must be finite");
+    ctm::EnvOptions o = to_options(opts, D * D);
+    check_precision(o.precision);
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    ctm::FullUpdate fu(ctx->c, D, gamma);
+    fu.run(A, B, H, tau, chi, o, sweeps, als_iters, A_out, B_out, errors);
+  });
+}
+
+int ctm_fu_trotter_step(ctm_context* ctx, double* A, double* B, int D, const double* H,
+                        double dbeta, int chi, const ctm_opts* opts, int sweeps, int als_iters,
+                        double* errors) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(A && B && H, "null argument");
+    CTM_REQUIRE(D >= 1 && D <= 8, "D must be 1..8");
+    CTM_REQUIRE(chi >= 1 && sweeps >= 0 && als_iters >= 0, "chi >= 1, sweeps and als_iters >= 0");
+    CTM_REQUIRE(std::isfinite(dbeta), "dbeta must be finite");
+    ctm::EnvOptions o = to_options(opts, D * D);
+    check_precision(o.precision);
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    const size_t sz = 4ull * D * D * D;
+    std::vector<double> An(sz), Bn(sz);
+    const int seq_gamma[5] = {0, 1, 2, 1, 0};
+    const double seq_t[5] = {0.5 * dbeta, 0.5 * dbeta, dbeta, 0.5 * dbeta, 0.5 * dbeta};
+    for (int i = 0; i < 5; ++i) {
+      const int g = seq_gamma[i];
+      ctm::FullUpdate fu(ctx->c, D, g);
+      fu.run(A, B, H + 16 * g, seq_t[i], chi, o, sweeps, als_iters, An.data(), Bn.data(),
+             errors ? errors + (size_t)i * (als_iters + 1) : nullptr);
+      std::memcpy(A, An.data(), sz * sizeof(double));
+      std::memcpy(B, Bn.data(), sz * sizeof(double));
+    }
   });
 }
 

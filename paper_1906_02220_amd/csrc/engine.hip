@@ -586,6 +586,14 @@ void Env::bond_metric(double* out, size_t len) {
   for (size_t i = 0; i < d4; ++i) out[i] *= inv;
 }
 
+void Env::ring_ket_bra_dev(double* out) {
+  CTM_REQUIRE(D > 0, "ring_ket_bra_dev needs a purification environment");
+  ring();
+  const long long dd[8] = {D, D, D, D, D, D, D, D};
+  const int pp[8] = {0, 2, 4, 6, 1, 3, 5, 7};
+  permute(ctx, E.d(), out, 8, dd, pp);
+}
+
 // <O> from the 16 x 16 matrix rho[q][p] = sum K[q,ket] E8[ket,bra] K[p,bra]:
 // <O> = sum_pq O[p][q] rho[q][p] / tr(rho).
 double Env::expect_op(const double* op, int op_dim) {

@@ -63,6 +63,10 @@ class Env {
   double kappa();
   void log_z(double* log_abs, double* sign);
   void bond_metric(double* host_out, size_t len);
+  // Unnormalised ring E of a purification environment reordered to
+  // [ket u,l,d,r][bra u,l,d,r] (D^4 x D^4), written to device memory.
+  void ring_ket_bra_dev(double* out);
+  const double* composite_dev() const { return Kc.d(); }  // 16 x D^4
   double expect_op(const double* op, int op_dim);
   double expect_tensor(const double* a_imp_host);
   void corner_spectra(double* host_out, size_t len);

@@ -108,6 +108,12 @@ SIGNATURES = {
                                        ctypes.POINTER(ctm_opts), ctypes.c_int, ctypes.c_int, _D,
                                        ctypes.c_double, ctypes.c_double, _D, _D, _D,
                                        ctypes.POINTER(ctm_grad_info)]),
+    "ctm_fu_bond_update": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int, _D,
+                                          ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctm_opts),
+                                          ctypes.c_int, ctypes.c_int, _D, _D, _D]),
+    "ctm_fu_trotter_step": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, _D, ctypes.c_double,
+                                           ctypes.c_int, ctypes.POINTER(ctm_opts), ctypes.c_int,
+                                           ctypes.c_int, _D]),
     "ctm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_timing_reset": (ctypes.c_int, [_P]),
     "ctm_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _LL, _D, _D]),
@@ -290,6 +296,43 @@ def grad_tensor(ctx, a, chi, sweeps, a_imp=None, w_log_kappa=1.0, w_expect=0.0,
                                  _dptr(ga), ctypes.byref(info))
     ctx.check(rc, "ctm_grad_tensor")
     return lk.value, ex.value, ga, _info_dict(info)
+
+
+def fu_bond_update(ctx, A, B, gamma, H, tau, chi, sweeps, als_iters, **kw):
+    """ctm_fu_bond_update: returns (A'', B'', errors) for A, B of shape
+    (2, 2, D, D, D)."""
+    A = _f64(A)
+    B = _f64(B)
+    D = A.shape[2]
+    if A.shape != (2, 2, D, D, D) or B.shape != A.shape:
+        raise ValueError("A and B must both have shape (2, 2, D, D, D)")
+    Hc = _f64(H)
+    o = default_opts(**kw)
+    A2 = np.zeros_like(A)
+    B2 = np.zeros_like(B)
+    errs = np.zeros(als_iters + 1)
+    rc = ctx.lib.ctm_fu_bond_update(ctx.h, _dptr(A), _dptr(B), D, gamma, _dptr(Hc), tau, chi,
+                                    ctypes.byref(o), sweeps, als_iters, _dptr(A2), _dptr(B2),
+                                    _dptr(errs))
+    ctx.check(rc, "ctm_fu_bond_update")
+    return A2, B2, errs
+
+
+def fu_trotter_step(ctx, A, B, H3, dbeta, chi, sweeps, als_iters, **kw):
+    """ctm_fu_trotter_step: returns (A, B, errors[5, als_iters + 1]) after one
+    second-order Trotter step with bond terms H3 = (H_x, H_y, H_z)."""
+    A = _f64(A).copy()
+    B = _f64(B).copy()
+    D = A.shape[2]
+    if A.shape != (2, 2, D, D, D) or B.shape != A.shape:
+        raise ValueError("A and B must both have shape (2, 2, D, D, D)")
+    Hs = _f64(np.stack([np.asarray(h, dtype=np.float64) for h in H3]))
+    o = default_opts(**kw)
+    errs = np.zeros((5, als_iters + 1))
+    rc = ctx.lib.ctm_fu_trotter_step(ctx.h, _dptr(A), _dptr(B), D, _dptr(Hs), dbeta, chi,
+                                     ctypes.byref(o), sweeps, als_iters, _dptr(errs))
+    ctx.check(rc, "ctm_fu_trotter_step")
+    return A, B, errs
 
 
 class Environment:
