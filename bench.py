@@ -288,6 +288,36 @@ def run_grad(ctm, synth, reps):
             "log_kappa": lk, "energy_bond": ex}
 
 
+def run_fu(ctm, synth, reps):
+    """Full-update bond update at the benchmark's shape: random D = 6
+    purification (seed 1234), gamma = z, Kitaev-Heisenberg bond term at
+    phi = -63 degrees, tau = 0.02; environment of the gated composite (4D = 24
+    inside, d = 36 outside) from 20 sweeps at chi = 72 in FP64; 10 ALS rounds.
+    Timed: `reps` calls after one untimed call, and the same with 0 rounds
+    for the ALS share."""
+    A, B = synth.random_purification(6, 1234)
+    H = synth.kitaev_heisenberg_bond(np.deg2rad(-63.0), 2)
+    ctx = ctm.Context(0)
+    ctm.fu_bond_update(ctx, A, B, 2, H, 0.02, 72, 20, 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A2, B2, errs = ctm.fu_bond_update(ctx, A, B, 2, H, 0.02, 72, 20, 10)
+    dt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctm.fu_bond_update(ctx, A, B, 2, H, 0.02, 72, 20, 0)
+    d0 = (time.perf_counter() - t0) / reps
+    ctx.close()
+    log("bench: full-update bond update %.1f ms (%.1f ms without ALS)" % (1e3 * dt, 1e3 * d0))
+    return {"workload": "one eeFU bond update: D=6 (seed 1234), gamma=z, KH phi=-63 deg, tau=0.02, "
+                        "environment of the gated composite from 20 sweeps at chi=72 (FP64), "
+                        "10 ALS rounds (216 x 216 normal matrices)",
+            "ms_per_bond_update": round(1e3 * dt, 2),
+            "ms_environment_and_setup": round(1e3 * d0, 2),
+            "ms_per_als_round": round(1e3 * (dt - d0) / 10, 3),
+            "error_start": errs[0], "error_after_10_rounds": errs[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +332,8 @@ def main():
                     help="environments of the batched-sweep measurement (0: skip it)")
     ap.add_argument("--grad", type=int, default=3,
                     help="timed calls of the gradient measurement (0: skip it)")
+    ap.add_argument("--fu", type=int, default=2,
+                    help="timed calls of the full-update measurement (0: skip it)")
     ap.add_argument("--modes", default="0,1,3,4",
                     help="precision modes to time (0 FP64, 1 FP32, 3/4 BF16 slices); FP64 always runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -390,6 +422,8 @@ def main():
         out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
     if args.grad > 0:
         out["grad"] = run_grad(ctm, synth, args.grad)
+    if args.fu > 0:
+        out["fu"] = run_fu(ctm, synth, args.fu)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(D, chi, seed)
