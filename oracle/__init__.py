@@ -18,6 +18,8 @@ brute         exact contraction of small finite lattices by a row transfer
 gates         two-site gate and its rank-4 split, used to build test inputs.
 fu            one full-update bond truncation: gate, environment of the
               gated composite, alternating least squares in its metric.
+transfer      the column transfer matrix of the environment, dense, and its
+              leading eigenvalues (correlation length).
 gradients     directional derivatives of the oracle's objectives (ln kappa,
               <O>) by fourth-order central differences: the reference for
               the hand-written adjoint of the HIP path.
