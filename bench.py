@@ -318,6 +318,28 @@ def run_fu(ctm, synth, reps):
             "error_start": errs[0], "error_after_10_rounds": errs[-1]}
 
 
+def run_xi(ctm, synth, reps):
+    """Correlation length of the benchmark environment: D = 6, chi = 72, seed
+    1234, 20 FP64 sweeps; the column transfer matrix with the site row
+    (dimension chi^2 d = 186624), 40 Arnoldi steps, 4 leading eigenvalues."""
+    A, B = synth.random_purification(6, 1234)
+    ctx = ctm.Context(0)
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 72)
+    env.sweep(20)
+    env.transfer_spectrum(0, True, 4, 40)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev, xi = env.transfer_spectrum(0, True, 4, 40)
+    dt = (time.perf_counter() - t0) / reps
+    env.close()
+    ctx.close()
+    log("bench: transfer spectrum %.1f ms, xi %.6f" % (1e3 * dt, xi))
+    eps = [float(-np.log(abs(e) / abs(ev[0]))) for e in ev[1:]]
+    return {"workload": "column transfer matrix (T1, a, T3) of the D=6 chi=72 environment after "
+                        "20 sweeps (dimension 186624), 40 Arnoldi steps",
+            "ms": round(1e3 * dt, 2), "xi": xi, "eps_2_3_4": eps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +444,8 @@ def main():
         out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
     if args.grad > 0:
         out["grad"] = run_grad(ctm, synth, args.grad)
+    if args.grad > 0:
+        out["xi"] = run_xi(ctm, synth, 2)
     if args.fu > 0:
         out["fu"] = run_fu(ctm, synth, args.fu)
     if not args.no_cpu_baseline:

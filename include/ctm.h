@@ -285,6 +285,20 @@ int ctm_fu_trotter_step(ctm_context* ctx, double* A, double* B, int D, const dou
                         double dbeta, int chi, const ctm_opts* opts, int sweeps, int als_iters,
                         double* errors);
 
+/* Leading eigenvalues of the transfer matrix of the environment, for the
+ * correlation length (Sec. IV quotes xi in lattice constants of the rhombic
+ * lattice).  direction 0: one column, v'[x',r,y'] = sum T1[x,m,x']
+ * a[m,l,n,r] T3[y',n,y] v[x,l,y]; direction 1: one row (T2, a rotated by
+ * 90 degrees, T4); site = 0 leaves the site tensor out (T1 and T3 joined over
+ * their inner leg).  `krylov` Arnoldi steps (2..64, capped at the dimension)
+ * from a start drawn with opts' seed of the environment; the nev leading
+ * Ritz values by decreasing magnitude go to re, im (host, nev entries,
+ * 1 <= nev <= krylov; missing ones are 0) and *xi = -1/ln|lambda_2/lambda_1|
+ * (0 if lambda_2 vanishes; may be null).  CTM_ENUMERIC if the Hessenberg QR
+ * does not converge. */
+int ctm_transfer_spectrum(ctm_env* env, int direction, int site, int nev, int krylov, double* re,
+                          double* im, double* xi);
+
 /* Kernel timing over the calls since the last reset, measured with HIP
  * events on the context's stream around every launch of one kernel class.
  * cls 0: FP64 GEMMs of the n x n x n half-system and cut products;

@@ -1,6 +1,7 @@
 // C ABI of the CTMRG library (declared in include/ctm.h).  Every entry point
 // converts library errors into status codes and records the message on the
 // context; no exception crosses the ABI.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -13,6 +14,7 @@
 #include "ctm.h"
 #include "adjoint.hpp"
 #include "fu.hpp"
+#include "transfer.hpp"
 #include "engine.hpp"
 
 // The context state is shared by the context handle and every environment
@@ -458,6 +460,34 @@ int ctm_fu_trotter_step(ctm_context* ctx, double* A, double* B, int D, const dou
              errors ? errors + (size_t)i * (als_iters + 1) : nullptr);
       std::memcpy(A, An.data(), sz * sizeof(double));
       std::memcpy(B, Bn.data(), sz * sizeof(double));
+    }
+  });
+}
+
+int ctm_transfer_spectrum(ctm_env* env, int direction, int site, int nev, int krylov, double* re,
+                          double* im, double* xi) {
+  if (!env) return CTM_EINVAL;
+  return guarded_c(env->owner_c, [&] {
+    CTM_REQUIRE(re && im, "null argument");
+    CTM_REQUIRE(krylov >= 2 && krylov <= 64, "krylov must be 2..64");
+    CTM_REQUIRE(nev >= 1 && nev <= krylov, "nev must be 1..krylov");
+    CTM_HIP(hipSetDevice(env->owner_c->device));
+    ctm::Transfer tr(*env->e, direction, site != 0);
+    std::vector<double> wr(64), wi(64);
+    const int k = tr.spectrum(krylov, env->e->opt.seed ^ 0x7a5fULL, wr.data(), wi.data());
+    std::vector<int> idx(k);
+    for (int i = 0; i < k; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+      return std::hypot(wr[a], wi[a]) > std::hypot(wr[b], wi[b]);
+    });
+    for (int i = 0; i < nev; ++i) {
+      re[i] = i < k ? wr[idx[i]] : 0.0;
+      im[i] = i < k ? wi[idx[i]] : 0.0;
+    }
+    if (xi) {
+      const double l1 = k > 0 ? std::hypot(wr[idx[0]], wi[idx[0]]) : 0.0;
+      const double l2 = k > 1 ? std::hypot(wr[idx[1]], wi[idx[1]]) : 0.0;
+      *xi = (l1 > 0.0 && l2 > 0.0) ? -1.0 / std::log(l2 / l1) : 0.0;
     }
   });
 }

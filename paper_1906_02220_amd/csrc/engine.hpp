@@ -16,6 +16,7 @@ struct EnvOptions {
 };
 
 class Grad;
+class Transfer;
 
 // Per-move record of the forward pass kept for the adjoint: the environment
 // before the move, the kept singular triplets of the cut matrix and the
@@ -37,6 +38,7 @@ struct TapeLayout {
 
 class Env {
   friend class Grad;
+  friend class Transfer;
 
  public:
   Env(Context& ctx, int d, int chi, const EnvOptions& opt);

@@ -114,6 +114,8 @@ SIGNATURES = {
     "ctm_fu_trotter_step": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, _D, ctypes.c_double,
                                            ctypes.c_int, ctypes.POINTER(ctm_opts), ctypes.c_int,
                                            ctypes.c_int, _D]),
+    "ctm_transfer_spectrum": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, _D, _D, _D]),
     "ctm_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_timing_reset": (ctypes.c_int, [_P]),
     "ctm_timing_get": (ctypes.c_int, [_P, ctypes.c_int, _LL, _D, _D]),
@@ -436,6 +438,18 @@ class Environment:
         self.ctx.check(self.ctx.lib.ctm_expect_tensor(self.h, _dptr(a_imp), ctypes.byref(v)),
                        "ctm_expect_tensor")
         return v.value
+
+    def transfer_spectrum(self, direction=0, site=True, nev=4, krylov=40):
+        """Leading transfer-matrix eigenvalues (complex, by decreasing
+        magnitude) and the correlation length (ctm_transfer_spectrum)."""
+        re = np.zeros(nev)
+        im = np.zeros(nev)
+        xi = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_transfer_spectrum(self.h, direction, 1 if site else 0, nev,
+                                                          krylov, _dptr(re), _dptr(im),
+                                                          ctypes.byref(xi)),
+                       "ctm_transfer_spectrum")
+        return re + 1j * im, xi.value
 
     def corner_spectra(self):
         out = np.empty(4 * self.chi)
