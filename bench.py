@@ -141,11 +141,12 @@ def read_traffic(mode):
 MODE_NAMES = {0: "f64", 1: "f32", 3: "bf16x3", 4: "bf16x4"}
 PRECISION_TEXT = {
     0: "FP64 MFMA throughout",
-    1: "a4/a5/a7/a9 contractions: FP32 MFMA, FP32 accumulation; projector SVD and small products FP64",
-    3: "a4/a5/a7/a9 contractions: 3 BF16 slices (6 slice products), FP32 accumulation over K chunks "
-       "of 128, FP64 chunk sums; projector SVD and small products FP64",
-    4: "a4/a5/a7/a9 contractions: 4 BF16 slices (10 slice products), FP32 accumulation over K chunks "
-       "of 128, FP64 chunk sums; projector SVD and small products FP64",
+    1: "a4/a5/a7 sweep contractions: FP32 MFMA, FP32 accumulation; projector SVD, small products "
+       "and the a9 ring FP64",
+    3: "a4/a5/a7 sweep contractions: 3 BF16 slices (6 slice products), FP32 accumulation over K "
+       "chunks of 128, FP64 chunk sums; projector SVD, small products and the a9 ring FP64",
+    4: "a4/a5/a7 sweep contractions: 4 BF16 slices (10 slice products), FP32 accumulation over K "
+       "chunks of 128, FP64 chunk sums; projector SVD, small products and the a9 ring FP64",
 }
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 3: 2500.0, 4: 2500.0}
 SLICE_PRODUCTS = {0: 1, 1: 1, 3: 6, 4: 10}

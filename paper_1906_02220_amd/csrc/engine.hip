@@ -502,8 +502,10 @@ void Env::ring() {
            out_rowmajor(t1.d(), dc));                               // [h,x][l,a]
   const int p3012[4] = {3, 0, 1, 2};
   permute(ctx, t1.d(), Lt.d(), 4, d4, p3012);                       // [a,h,x,l]
-  gemm_mixed(ctx, opt.precision, d * d, d * d, chi * chi, 1.0, rowmajor(U.d(), chi * chi),
-             rowmajor(Lt.d(), d * d), 0.0, out_rowmajor(t2.d(), d * d));  // [u,r][x,l]
+  // FP64 in every precision mode: the ring is contracted once per observable,
+  // outside the sweeps, and its rounding is what kappa's error would follow
+  gemm_f64(ctx, d * d, d * d, chi * chi, 1.0, rowmajor(U.d(), chi * chi), rowmajor(Lt.d(), d * d),
+           0.0, out_rowmajor(t2.d(), d * d));  // [u,r][x,l]
   const long long f4[4] = {d, d, d, d};
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t2.d(), E.d(), 4, f4, p0321);                        // [u,l,x,r]

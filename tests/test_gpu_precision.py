@@ -1,9 +1,9 @@
 """Reduced-precision contraction modes against the FP64 oracle.
 
-The a4/a5/a7/a9 contractions (enlarged corners, halves and cut matrix,
-site-tensor absorption, ring) run in FP32 (one product) or as BF16 slice
-products (CTM_PREC_BF16X3 / X4); the projector SVD, the small products and
-the norm normalisation stay FP64.  The gate for every mixed mode is the
+The a4/a5/a7 contractions of the sweeps (enlarged corners, halves and cut
+matrix, site-tensor absorption) run in FP32 (one product) or as BF16 slice
+products (CTM_PREC_BF16X3 / X4); the projector SVD, the small products, the
+a9 ring of the observables and the norm normalisation stay FP64.  The gate for every mixed mode is the
 mixed-mode target on the environment norm, 1e-7 relative on kappa, applied
 to <H_bond> (absolute) as well for the slice modes; CTM_PREC_BF16X4 is also
 held to 1e-8 on kappa.  (<H_bond> is a small number formed by cancellation over the ring,
