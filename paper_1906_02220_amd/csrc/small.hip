@@ -344,13 +344,20 @@ __device__ inline double lane8_sum(double v) {
 
 // One workgroup per matrix, one-sided Jacobi (Hestenes) on the columns of A
 // (A = B, or B^T when trans != 0).  Columns of the working matrix and of V
-// are kept column-major in LDS with an odd stride; each round of the circle
+// are kept column-major in LDS, 8 RPT rows each, with the 8-row blocks of
+// column j permuted by block ^ (j & 3): the 8-lane groups of a wave read
+// columns whose indices differ by one, so the groups hit different banks;
+// each round of the circle
 // schedule (precomputed in LDS) rotates the bp/2 disjoint column pairs in
 // parallel, 8 lanes per pair, each lane holding RPT rows of the pair in
 // registers.  The rotation (the smaller root t of t^2 + 2 zeta t - 1 = 0,
 // c = 1/sqrt(1 + t^2), s = c t) uses Newton-refined reciprocals.  On exit
 // A = U diag(s) V^T with s descending; with trans == 0 X = U, Y = V, with
 // trans != 0 X = V, Y = U (so that always B = X diag(s) Y^T).
+// LDS row of logical row i in column j (a permutation of the 8-row blocks
+// inside each aligned group of 4 blocks).
+__device__ inline int jac_row(int i, int j) { return i ^ (8 * (j & 3)); }
+
 template <int RPT>
 __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restrict__ Bm, int b,
                                                          long long bstride, long long sstride,
@@ -360,7 +367,8 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
                                                          int want_vec, int trans) {
   extern __shared__ double lds[];
   const int bp = b + (b & 1);
-  constexpr int ld = 8 * RPT + 1;  // odd stride, rows b..8*RPT-1 stay zero
+  constexpr int ld = 8 * RPT;  // rows b..8*RPT-1 stay zero
+  static_assert(RPT % 4 == 0, "the block permutation needs groups of 4 blocks");
   double* Wc = lds;                                  // bp columns
   double* Vc = want_vec ? lds + bp * ld : nullptr;   // bp columns
   double* sv = lds + (want_vec ? 2 : 1) * bp * ld;   // bp singular values
@@ -376,8 +384,9 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
     const int j = idx / ld, i = idx - (idx / ld) * ld;
     double v = 0.0;
     if (j < b && i < b) v = trans ? B[(long long)j * b + i] : B[(long long)i * b + j];
-    Wc[idx] = v;
-    if (Vc) Vc[idx] = (i == j && i < b) ? 1.0 : 0.0;
+    const int ph = j * ld + jac_row(i, j);
+    Wc[ph] = v;
+    if (Vc) Vc[ph] = (i == j && i < b) ? 1.0 : 0.0;
   }
   const int P = bp / 2;
   const int m = bp - 1;
@@ -403,11 +412,18 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
         const int q = sched[2 * (r * P + pi) + 1];
         double* wp = Wc + p * ld + sub;
         double* wq = Wc + q * ld + sub;
+        // offsets of the logical rows sub + 8k, k = 4g + e: 32 g + op[e]
+        int op[4], oq[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          op[e] = 8 * (e ^ (p & 3));
+          oq[e] = 8 * (e ^ (q & 3));
+        }
         double xp[RPT], xq[RPT];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-          xp[k] = wp[8 * k];
-          xq[k] = wq[8 * k];
+          xp[k] = wp[32 * (k >> 2) + op[k & 3]];
+          xq[k] = wq[32 * (k >> 2) + oq[k & 3]];
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -439,8 +455,8 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
           const double s = c * tt;
 #pragma unroll
           for (int k = 0; k < RPT; ++k) {
-            wp[8 * k] = c * xp[k] - s * xq[k];
-            wq[8 * k] = s * xp[k] + c * xq[k];
+            wp[32 * (k >> 2) + op[k & 3]] = c * xp[k] - s * xq[k];
+            wq[32 * (k >> 2) + oq[k & 3]] = s * xp[k] + c * xq[k];
           }
           if (Vc) {
             double* vp = Vc + p * ld + sub;
@@ -448,13 +464,13 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
             double yp[RPT], yq[RPT];
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
-              yp[k] = vp[8 * k];
-              yq[k] = vq[8 * k];
+              yp[k] = vp[32 * (k >> 2) + op[k & 3]];
+              yq[k] = vq[32 * (k >> 2) + oq[k & 3]];
             }
 #pragma unroll
             for (int k = 0; k < RPT; ++k) {
-              vp[8 * k] = c * yp[k] - s * yq[k];
-              vq[8 * k] = s * yp[k] + c * yq[k];
+              vp[32 * (k >> 2) + op[k & 3]] = c * yp[k] - s * yq[k];
+              vq[32 * (k >> 2) + oq[k & 3]] = s * yp[k] + c * yq[k];
             }
           }
           if (sub == 0) {
@@ -478,7 +494,10 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
   // singular values and ordering
   for (int j = t; j < bp; j += nt) {
     double s = 0.0;
-    for (int i = 0; i < b; ++i) s += Wc[j * ld + i] * Wc[j * ld + i];
+    for (int i = 0; i < b; ++i) {
+      const double w = Wc[j * ld + jac_row(i, j)];
+      s += w * w;
+    }
     s = sqrt(s);
     if (!isfinite(s)) bad = 1;
     sv[j] = s;
@@ -498,11 +517,11 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
     if (Uo) {
       double* X = Uo + blockIdx.x * bstride;
       const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-      for (int i = 0; i < b; ++i) X[(long long)i * b + rank] = Wc[j * ld + i] * inv;
+      for (int i = 0; i < b; ++i) X[(long long)i * b + rank] = Wc[j * ld + jac_row(i, j)] * inv;
     }
     if (Vo && Vc) {
       double* Y = Vo + blockIdx.x * bstride;
-      for (int i = 0; i < b; ++i) Y[(long long)i * b + rank] = Vc[j * ld + i];
+      for (int i = 0; i < b; ++i) Y[(long long)i * b + rank] = Vc[j * ld + jac_row(i, j)];
     }
   }
   if (t == 0 && (bad || sweep >= 60)) *err = 1;
@@ -679,7 +698,7 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
   const int bp = b + (b & 1);
   int rpt = (b + 7) / 8;
   rpt = rpt <= 4 ? 4 : (rpt <= 8 ? 8 : (rpt <= 12 ? 12 : 16));
-  const int ld = 8 * rpt + 1;
+  const int ld = 8 * rpt;
   const size_t lds = ((vec ? 2 : 1) * (size_t)bp * ld + bp) * sizeof(double) +
                      (size_t)(bp - 1) * bp + 16;
   CTM_REQUIRE(lds <= 160 * 1024, "jacobi_svd: matrix too large for LDS");
