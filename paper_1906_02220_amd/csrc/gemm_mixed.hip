@@ -187,6 +187,15 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
 
 // ------------------------------------------------------------ BF16 slice GEMM
 
+// LDS position (in BF16 units) of the 16-byte chunk c (8 consecutive k) of
+// row r in a 32-wide K step: rows are 64 bytes, unpadded, and the chunk index
+// is XORed with ((r >> 1) ^ (r >> 2)) & 3.  Both the operand reads (16
+// consecutive rows, one chunk) and the tile stores (4 consecutive rows, all
+// four chunks) then touch 16 distinct 16-byte bank groups, whether LDS serves
+// a 128-bit access 8 or 16 lanes at a time; a padded 80-byte row left the
+// stores 2-way conflicted (half of all LDS cycles in the counters).
+__device__ inline int slice_pos(int r, int c) { return r * 32 + ((c ^ (((r >> 1) ^ (r >> 2)) & 3)) << 3); }
+
 // C (M x N, row stride ldc, FP64) = A B from the slices Aq[S][M][Kp] and
 // Bq[S][N][Kp] (B stored transposed) and the row / column maxima.  128 x 128
 // tile, 8 waves as 4 x 2, each wave 32 x 64 (2 x 4 MFMA tiles); K steps of
@@ -196,10 +205,10 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     int M, int N, int Kp, const __bf16* __restrict__ Aq, const __bf16* __restrict__ Bq,
     const double* __restrict__ amax, const double* __restrict__ bmax, double* __restrict__ C,
     int ldc) {
-  constexpr int BM = 128, BN = 128, BK = 32, PITCH = BK + 8;  // bf16 units; 80-byte rows
+  constexpr int BM = 128, BN = 128, BK = 32;
   constexpr int TI = 2, TJ = 4;
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][S][BM * PITCH];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][BN * PITCH];
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][S][BM * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][BN * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
   int tm, tn;
@@ -211,6 +220,7 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
   const bool arow_ok = (m0 + lrow) < M, brow_ok = (n0 + lrow) < N;
   const __bf16* ag = Aq + (long long)(m0 + lrow) * Kp + lk;
   const __bf16* bg = Bq + (long long)(n0 + lrow) * Kp + lk;
+  const int spos = slice_pos(lrow, tid & 3);
   u4 ra[S], rb[S];
   auto load = [&](int kt) {
 #pragma unroll
@@ -222,8 +232,8 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
   auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      *(u4*)(&As[buf][i][lrow * PITCH + lk]) = ra[i];
-      *(u4*)(&Bs[buf][i][lrow * PITCH + lk]) = rb[i];
+      *(u4*)(&As[buf][i][spos]) = ra[i];
+      *(u4*)(&Bs[buf][i][spos]) = rb[i];
     }
   };
   f4 acc0[TI][TJ], accr[TI][TJ];
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
     }
-  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int fr = lane & 15, fc = lane >> 4;
   auto flush = [&]() {
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -262,12 +272,12 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int s = 0; s < S; ++s)
-        a[i][s] = *(const bf8*)(&As[buf][s][(wm + 16 * i + fr) * PITCH + fk]);
+        a[i][s] = *(const bf8*)(&As[buf][s][slice_pos(wm + 16 * i + fr, fc)]);
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
       bf8 b[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) b[s] = *(const bf8*)(&Bs[buf][s][(wn + 16 * j + fr) * PITCH + fk]);
+      for (int s = 0; s < S; ++s) b[s] = *(const bf8*)(&Bs[buf][s][slice_pos(wn + 16 * j + fr, fc)]);
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
         acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[0], acc0[i][j], 0, 0, 0);
