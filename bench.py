@@ -204,25 +204,37 @@ def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
             "roofline": roof, "fu_ms": fu_ms, "kappa": kappa, "energy_bond": e_h}
 
 
-def run_batch(ctm, torch, synth, count, warm, steps):
+def run_batch(ctm, torch, synth, count, warm, steps, uniform=None):
     """Batched sweeps: `count` independent purifications with (D, chi) drawn
     uniformly from {4,5,6,7} x {32,48,72,96} (seed 777), A and B i.i.d.
     N(0,1) in FP32 (seed 778 + i), scaled to unit max-abs, contractions in
     the FP32 mode.  Timed: `steps` sweeps of the whole batch after `warm`,
     with the environments in turn on one context, concurrently on one
-    context each, and concurrently with autotuned tilings and graph replay."""
-    rng = np.random.default_rng(777)
-    Ds = rng.choice([4, 5, 6, 7], size=count).tolist()
-    chis = rng.choice([32, 48, 72, 96], size=count).tolist()
-    cfg = list(zip(Ds, chis))
+    context each, concurrently with autotuned tilings and graph replay, and in
+    lock-step with the n x n x n products of all environments grouped into
+    persistent launches (one context each).  With `uniform` = (D, chi) every
+    environment has that shape instead."""
+    if uniform is None:
+        rng = np.random.default_rng(777)
+        Ds = rng.choice([4, 5, 6, 7], size=count).tolist()
+        chis = rng.choice([32, 48, 72, 96], size=count).tolist()
+        cfg = list(zip(Ds, chis))
+        what = "(D, chi) uniform on {4,5,6,7} x {32,48,72,96} (seed 777)"
+        variants = (("in_turn", True, False, False, False),
+                    ("concurrent", False, False, False, False),
+                    ("concurrent_autotuned_graphs", False, True, True, False),
+                    ("lockstep_grouped", False, False, False, True))
+    else:
+        cfg = [tuple(uniform)] * count
+        what = "all D=%d, chi=%d" % tuple(uniform)
+        variants = (("in_turn", True, False, False, False),
+                    ("concurrent_autotuned_graphs", False, True, True, False),
+                    ("lockstep_grouped", False, False, False, True))
     work = sum(2.0 * move_macs(chi, D * D) * 4 for D, chi in cfg)
-    out = {"workload": "%d purifications, (D, chi) uniform on {4,5,6,7} x {32,48,72,96} "
-                       "(seed 777), FP32 entries, FP32 contraction mode" % count,
+    out = {"workload": "%d purifications, %s, FP32 entries, FP32 contraction mode" % (count, what),
            "envs": [[int(D), int(chi)] for D, chi in cfg], "sweeps_timed": steps,
            "unit": "GFLOP/s (sum over the batch, algorithmic)"}
-    for name, one_ctx, tune, graphs in (("in_turn", True, False, False),
-                                        ("concurrent", False, False, False),
-                                        ("concurrent_autotuned_graphs", False, True, True)):
+    for name, one_ctx, tune, graphs, grouped in variants:
         ctxs = [ctm.Context(0)] if one_ctx else [ctm.Context(0) for _ in cfg]
         for c in ctxs:
             c.autotune(tune)
@@ -232,21 +244,22 @@ def run_batch(ctm, torch, synth, count, warm, steps):
             A, B = synth.random_purification(D, 778 + i, dtype=np.float32)
             envs.append(ctm.Environment.from_purification(ctxs[0 if one_ctx else i], A, B, 2, chi,
                                                           precision=ctm.CTM_PREC_F32))
-        ctm.sweep_batch(envs, warm)
+        ctm.sweep_batch(envs, warm, grouped=grouped)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctm.sweep_batch(envs, steps)
+        ctm.sweep_batch(envs, steps, grouped=grouped)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = {"value": round(work * steps / dt / 1e9, 2),
                      "ms_per_batch_sweep": round(1e3 * dt / steps, 3)}
-        log("bench: batch %s: %.1f ms per batch sweep" % (name, 1e3 * dt / steps))
+        log("bench: batch %s %s: %.1f ms per batch sweep" % (what, name, 1e3 * dt / steps))
         for e in envs:
             e.close()
         for c in ctxs:
             c.close()
-    out["speedup_vs_in_turn"] = round(out["concurrent_autotuned_graphs"]["value"] /
-                                      out["in_turn"]["value"], 3)
+    best = max(("concurrent_autotuned_graphs", "lockstep_grouped"), key=lambda k: out[k]["value"])
+    out["best"] = best
+    out["speedup_vs_in_turn"] = round(out[best]["value"] / out["in_turn"]["value"], 3)
     return out
 
 
@@ -443,6 +456,7 @@ def main():
     }
     if args.batch > 0:
         out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
+        out["batch_uniform"] = run_batch(ctm, torch, synth, args.batch, 3, 4, uniform=(4, 32))
     if args.grad > 0:
         out["grad"] = run_grad(ctm, synth, args.grad)
     if args.grad > 0:

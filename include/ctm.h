@@ -156,6 +156,22 @@ int ctm_sweep(ctm_env* env, int max_sweeps, double tol, int* sweeps_done, double
 int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol,
                     int* sweeps_done, double* delta);
 
+/* The same sweeps in lock-step (Sec. III's CTMRG run per state, many states
+ * at once): each move direction of a round takes the enlarged corners of
+ * every unconverged environment on its own stream, then the two half-system
+ * products and the cut matrix (the n x n x n contractions of the absorption
+ * move) of all of them as one persistent grouped launch per kernel kind on
+ * the first environment's context stream, whose workgroups claim tiles from a
+ * device counter, then the projector SVDs and absorptions again on each
+ * environment's stream.  Products are grouped only where ctm_sweep would run
+ * the same FP64 or FP32 tile kernel without split-K (other products, such as
+ * those of the BF16 slice modes, run on the environment's own stream), so the
+ * results are bit-identical to ctm_sweep.  Every environment must live on the
+ * first one's device; a captured sweep graph of an environment is dropped.
+ * Arguments, return codes and error reporting as ctm_sweep_batch. */
+int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, double tol,
+                            int* sweeps_done, double* delta);
+
 /* One absorption move: direction 0 left, 1 up, 2 right, 3 down. */
 int ctm_move(ctm_env* env, int direction);
 

@@ -492,6 +492,126 @@ int ctm_transfer_spectrum(ctm_env* env, int direction, int site, int nev, int kr
   });
 }
 
+int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, double tol,
+                            int* sweeps_done, double* delta) {
+  if (!envs || count < 0) return CTM_EINVAL;
+  if (count == 0) return CTM_OK;
+  for (int i = 0; i < count; ++i)
+    if (!envs[i]) return CTM_EINVAL;
+  std::vector<int> done(count, 0), active(count, 1), kind(count, 0);
+  std::vector<double> dl(count, INFINITY);
+  std::vector<hipEvent_t> ev(count, nullptr);
+  hipEvent_t evg = nullptr;
+  ctm::Context* gc = envs[0]->owner_c;
+  // the grouped products run on a stream of their own (default priority), so
+  // that no member's own work sits between two grouped launches
+  ctm::Context grp;
+  int cur = -1;
+  auto drain = [&] {
+    for (int i = 0; i < count; ++i) (void)hipStreamSynchronize(envs[i]->owner_c->stream);
+    if (grp.stream) (void)hipStreamSynchronize(grp.stream);
+  };
+  const int rc = guarded_c(gc, [&] {
+    CTM_REQUIRE(max_sweeps >= 0, "max_sweeps must be >= 0");
+    for (int i = 0; i < count; ++i) {
+      CTM_REQUIRE(envs[i]->owner_c->device == gc->device,
+                  "grouped batch: every environment must live on the first one's device");
+      for (int j = 0; j < i; ++j)
+        CTM_REQUIRE(envs[i] != envs[j], "an environment appears twice in the batch");
+    }
+    CTM_HIP(hipSetDevice(gc->device));
+    grp.device = gc->device;
+    grp.num_cus = gc->num_cus;
+    CTM_HIP(hipStreamCreateWithFlags(&grp.own_stream, hipStreamNonBlocking));
+    grp.stream = grp.own_stream;
+    ctm::DevBuf counter;
+    counter.alloc(sizeof(int));
+    try {
+      for (int i = 0; i < count; ++i) CTM_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+      CTM_HIP(hipEventCreateWithFlags(&evg, hipEventDisableTiming));
+      std::vector<ctm::GroupProblem> probs(3 * (size_t)count);
+      std::vector<ctm::GroupProblem> first[3], second[3];  // by kernel kind 1, 2
+      for (int s = 0; s < max_sweeps; ++s) {
+        for (int m = 0; m < 4; ++m) {
+          const int k = ctm::kSweepOrder[m];
+          for (auto& v : first) v.clear();
+          for (auto& v : second) v.clear();
+          for (int i = 0; i < count; ++i) {
+            if (!active[i]) continue;
+            cur = i;
+            ctm::Env& e = *envs[i]->e;
+            e.move_front(k);
+            kind[i] = e.cut_products(k, &probs[3 * (size_t)i]);
+            if (kind[i] == 0) continue;
+            first[kind[i]].push_back(probs[3 * (size_t)i]);
+            first[kind[i]].push_back(probs[3 * (size_t)i + 1]);
+            second[kind[i]].push_back(probs[3 * (size_t)i + 2]);
+            CTM_HIP(hipEventRecord(ev[i], envs[i]->owner_c->stream));
+            CTM_HIP(hipStreamWaitEvent(grp.stream, ev[i], 0));
+          }
+          cur = -1;
+          // the half-system products of every grouped environment in one
+          // launch per kernel kind, then their cut matrices
+          for (int kd = 1; kd <= 2; ++kd)
+            if (!first[kd].empty())
+              ctm::gemm_grouped(grp, kd, first[kd].data(), (int)first[kd].size(), (int*)counter.p);
+          for (int kd = 1; kd <= 2; ++kd)
+            if (!second[kd].empty())
+              ctm::gemm_grouped(grp, kd, second[kd].data(), (int)second[kd].size(), (int*)counter.p);
+          CTM_HIP(hipEventRecord(evg, grp.stream));
+          for (int i = 0; i < count; ++i) {
+            if (!active[i]) continue;
+            cur = i;
+            ctm::Env& e = *envs[i]->e;
+            if (kind[i] == 0) e.move_products(k);
+            else CTM_HIP(hipStreamWaitEvent(envs[i]->owner_c->stream, evg, 0));
+            e.move_back(k);
+          }
+        }
+        for (int i = 0; i < count; ++i)
+          if (active[i]) {
+            cur = i;
+            envs[i]->e->sweep_tail_eager();
+          }
+        int left = 0;
+        for (int i = 0; i < count; ++i) {
+          if (!active[i]) continue;
+          cur = i;
+          CTM_HIP(hipStreamSynchronize(envs[i]->owner_c->stream));
+          dl[i] = envs[i]->e->sweep_finish("ctm_sweep_batch_grouped");
+          ++done[i];
+          if (tol > 0.0 && dl[i] < tol) active[i] = 0;
+          left += active[i];
+        }
+        if (left == 0) break;
+      }
+      drain();
+    } catch (const ctm::Error& e) {
+      drain();
+      for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      if (evg) (void)hipEventDestroy(evg);
+      throw ctm::Error(e.code, cur >= 0 ? "environment " + std::to_string(cur) + ": " + e.what()
+                                        : std::string(e.what()));
+    }
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (evg) (void)hipEventDestroy(evg);
+  });
+  for (int i = 0; i < count; ++i) {
+    if (sweeps_done) sweeps_done[i] = done[i];
+    if (delta) delta[i] = dl[i];
+  }
+  if (rc != CTM_OK) return rc;
+  if (tol > 0.0)
+    for (int i = 0; i < count; ++i)
+      if (!(dl[i] < tol)) {
+        gc->last_error = "max_sweeps reached before tol";
+        return CTM_ENOTCONV;
+      }
+  return CTM_OK;
+}
+
 int ctm_move(ctm_env* env, int direction) {
   if (!env) return CTM_EINVAL;
   return guarded_c(env->owner_c, [&] {

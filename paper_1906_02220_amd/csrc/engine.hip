@@ -292,11 +292,16 @@ void Env::svd_top(const double* MtP, int k) {
 
 // a4 - a7: one absorption move (left move of frame k).
 void Env::move(int k) {
-  k &= 3;
-  const int dc = d * chi;
   const double W = 2.0 * (5.0 * chi * chi * std::pow((double)d, 4) + 3.0 * std::pow((double)n, 3) +
                           8.0 * std::pow((double)chi, 3) * d * d + 6.0 * std::pow((double)chi, 3) * d);
   ScopedTimer tmove(ctx, 2, W);
+  move_front(k);
+  move_products(k);
+  move_back(k);
+}
+
+void Env::move_front(int k) {
+  k &= 3;
   const TapeLayout tl(chi, d);
   if (tape_slot) {
     copy_dev(ctx, tape_slot + tl.c, Call.d(), 4ull * chi * chi);
@@ -304,14 +309,41 @@ void Env::move(int k) {
   }
   for (int r = 0; r < 4; ++r)
     if (!qvalid[(k + r) & 3]) corner(k + r);
+}
+
+// a5: halves and the cut matrix
+void Env::move_products(int k) {
+  k &= 3;
   const int q0 = k, q1 = (k + 1) & 3, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
-  // a5: halves and the cut matrix
   gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Qb[q0].d(), n), rowmajor(Qb[q1].d(), n),
              0.0, out_rowmajor(U.d(), n), 1, 0);
   gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Qb[q2].d(), n), rowmajor(Qb[q3].d(), n),
              0.0, out_rowmajor(Lt.d(), n), 1, 0);
   gemm_mixed(ctx, opt.precision, n, n, n, 1.0, rowmajor(Lt.d(), n), rowmajor(U.d(), n), 0.0,
              out_rowmajor(Mt.d(), n), 1, 0);
+}
+
+int Env::cut_products(int k, GroupProblem* probs) {
+  k &= 3;
+  const int q0 = k, q1 = (k + 1) & 3, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
+  const double* ops[3][2] = {{Qb[q0].d(), Qb[q1].d()}, {Qb[q2].d(), Qb[q3].d()}, {Lt.d(), U.d()}};
+  double* outs[3] = {U.d(), Lt.d(), Mt.d()};
+  int kind = -1;
+  for (int i = 0; i < 3; ++i) {
+    const int ki = grouped_kind(ctx, opt.precision, n, n, n, rowmajor(ops[i][0], n),
+                                rowmajor(ops[i][1], n), out_rowmajor(outs[i], n));
+    if (kind >= 0 && ki != kind) return 0;
+    kind = ki;
+    probs[i] = GroupProblem{ops[i][0], ops[i][1], outs[i], n, n, n, n, n, n};
+  }
+  return kind;
+}
+
+void Env::move_back(int k) {
+  k &= 3;
+  const int dc = d * chi;
+  const TapeLayout tl(chi, d);
+  const int q0 = k, q2 = (k + 2) & 3, q3 = (k + 3) & 3;
   // a6: projectors
   svd_top(Mt.d(), k);
   const int kk = std::min(chi, b);
@@ -393,11 +425,19 @@ int Env::sweep(int max_sweeps, double tol, int* done, double* delta_out) {
 }
 
 void Env::sweep_body() {
-  static const int order[4] = {0, 2, 1, 3};
   int* err = (int*)iflags.p + 1;
-  for (int i = 0; i < 4; ++i) move(order[i]);
+  for (int i = 0; i < 4; ++i) move(kSweepOrder[i]);
   jacobi_svd(ctx, Call.d(), chi, nullptr, spec_s.d(), nullptr, err, 4, (long long)chi * chi, chi);
   spectra_delta(ctx, spec_s.d(), spec_old.d(), chi, scal.d());
+}
+
+void Env::sweep_tail_eager() {
+  if (gexec) drop_graph();
+  int* err = (int*)iflags.p + 1;
+  jacobi_svd(ctx, Call.d(), chi, nullptr, spec_s.d(), nullptr, err, 4, (long long)chi * chi, chi);
+  spectra_delta(ctx, spec_s.d(), spec_old.d(), chi, scal.d());
+  CTM_HIP(hipMemcpyAsync(hbox, scal.d(), sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  CTM_HIP(hipMemcpyAsync(hbox + 1, iflags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
 }
 
 // A sweep may be captured once every direction runs warm (so the host takes

@@ -5,6 +5,9 @@
 
 namespace ctm {
 
+// Move directions of one sweep: left, right, up, down.
+constexpr int kSweepOrder[4] = {0, 2, 1, 3};
+
 struct EnvOptions {
   int precision = 0;
   double eps_cut = 1e-12;
@@ -52,6 +55,20 @@ class Env {
   void init_boundary();
 
   void move(int k);              // left move in the frame rotated k times
+  // The three parts of move(k), for batches run in lock-step: the tape record
+  // and the enlarged corners; the two half-system products and the cut matrix
+  // (a5); the projectors and the absorption (a6, a7).
+  void move_front(int k);
+  void move_products(int k);
+  void move_back(int k);
+  // The products of move_products(k) as grouped problems: U and Lt (independent)
+  // in probs[0..1], then Mt = Lt U in probs[2].  Returns the kernel kind of
+  // grouped_kind, or 0 if this environment has to run them itself.
+  int cut_products(int k, GroupProblem* probs);
+  // The rest of a sweep after its four moves: corner spectra and delta, then
+  // the copies to pinned host memory that sweep_finish reads.  Drops a
+  // captured sweep graph (the next graph-enabled sweep captures a new one).
+  void sweep_tail_eager();
   int sweep(int max_sweeps, double tol, int* done, double* delta);
   // One sweep without waiting for it: the four moves and the corner-spectrum
   // delta (replayed from a captured HIP graph when the context allows graphs

@@ -45,11 +45,18 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 // Split-K: blockIdx.z selects the K chunk [z kchunk, (z + 1) kchunk); with
 // ksplit > 1 the chunk's partial product goes to W (row stride N, one M x N
 // slab per (batch, chunk)) for the fixed-order reduction.
-template <int BM, int BN, int BK, int WGM, int WGN, int TAG>
-__global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
-    int M, int N, int K, const double* __restrict__ A, int lda, long long abs_,
-    const double* __restrict__ B, int ldb, long long bbs, double* __restrict__ C, int ldc,
-    long long cbs, int ksplit, int kchunk, double* __restrict__ W) {
+// One BM x BN tile of C = A B at (m0, n0) over the K range [kbeg, kend),
+// for dgemm_rr and the grouped kernel: 16-byte global loads into registers,
+// A staged [m][k] and B [k][n] in double-buffered LDS (one barrier per K
+// tile), and a plain store of the accumulators.  An alpha / beta epilogue
+// here costs enough registers to drop the occupancy to two workgroups per
+// CU, so the dispatchers send only C = A B products to it.
+template <int BM, int BN, int BK, int WGM, int WGN>
+__device__ __forceinline__ void rr_tile(int M, int N, const double* __restrict__ A, int lda,
+                                        const double* __restrict__ B, int ldb,
+                                        double* __restrict__ C, int ldc, int m0, int n0, int kbeg,
+                                        int kend, double (*As)[BM * (BK + 2)],
+                                        double (*Bs)[BK * (BN + 2)]) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TI = WM / 16, TJ = WN / 16;
@@ -59,23 +66,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
   static_assert(AV >= 1 && BV >= 1 && (BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0,
                 "tile does not split evenly into 16-byte loads");
   static_assert(TI * 16 == WM && TJ * 16 == WN, "wave tile must be a multiple of 16");
-  __shared__ double As[2][BM * SA];
-  __shared__ double Bs[2][BK * SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
-  int tm, tn;
-  xcd_tile<8>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
-  const int m0 = tm * BM, n0 = tn * BN;
-  A += blockIdx.y * abs_;
-  B += blockIdx.y * bbs;
-  const int kbeg = blockIdx.z * kchunk;
-  const int kend = min(K, kbeg + kchunk);
-  if (ksplit > 1) {
-    C = W + ((long long)blockIdx.y * ksplit + blockIdx.z) * ((long long)M * N);
-    ldc = N;
-  } else {
-    C += blockIdx.y * cbs;
-  }
   const bool full_m = (m0 + BM <= M), full_n = (n0 + BN <= N);
 
   d2v ra[AV], rb[BV];
@@ -148,9 +140,6 @@ __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
     __syncthreads();
     buf ^= 1;
   }
-  // Plain store of the accumulators: an alpha / beta epilogue here costs
-  // enough registers to drop the occupancy to two workgroups per CU, so the
-  // dispatcher sends only C = A B products to this kernel.
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -160,6 +149,57 @@ __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
         const int gm = m0 + wm + i * 16 + 4 * r + lk, gn = n0 + wn + j * 16 + lr;
         if (gm < M && gn < N) C[gm * ldc + gn] = acc[i][j][r];
       }
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int TAG>
+__global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
+    int M, int N, int K, const double* __restrict__ A, int lda, long long abs_,
+    const double* __restrict__ B, int ldb, long long bbs, double* __restrict__ C, int ldc,
+    long long cbs, int ksplit, int kchunk, double* __restrict__ W) {
+  __shared__ double As[2][BM * (BK + 2)];
+  __shared__ double Bs[2][BK * (BN + 2)];
+  int tm, tn;
+  xcd_tile<8>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
+  A += blockIdx.y * abs_;
+  B += blockIdx.y * bbs;
+  if (ksplit > 1) {
+    C = W + ((long long)blockIdx.y * ksplit + blockIdx.z) * ((long long)M * N);
+    ldc = N;
+  } else {
+    C += blockIdx.y * cbs;
+  }
+  const int kbeg = blockIdx.z * kchunk;
+  rr_tile<BM, BN, BK, WGM, WGN>(M, N, A, lda, B, ldb, C, ldc, tm * BM, tn * BN, kbeg,
+                                min(K, kbeg + kchunk), As, Bs);
+}
+
+// Grouped products: one persistent launch over a table of independent
+// C = A B problems (row-major, the dgemm_rr conditions), tiles numbered
+// problem by problem and claimed one at a time from a device counter, which
+// the host clears before the launch.  Every tile is computed exactly as
+// dgemm_rr computes it without split-K, so the results do not depend on which
+// workgroup takes which tile.  Each workgroup leaves once a claim passes the
+// last tile.
+template <int BM, int BN, int BK, int WGM, int WGN>
+__global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr_grouped(GroupTable tab,
+                                                                    int* __restrict__ counter) {
+  __shared__ double As[2][BM * (BK + 2)];
+  __shared__ double Bs[2][BK * (BN + 2)];
+  __shared__ int claim;
+  for (;;) {
+    if (threadIdx.x == 0) claim = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = claim;
+    __syncthreads();
+    if (t >= tab.total) break;
+    int p = 0;
+    while (p + 1 < tab.count && tab.tile_start[p + 1] <= t) ++p;
+    const GroupProblem& q = tab.p[p];
+    const int local = t - tab.tile_start[p];
+    const int ntn = (q.N + BN - 1) / BN;
+    rr_tile<BM, BN, BK, WGM, WGN>(q.M, q.N, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, (local / ntn) * BM,
+                                  (local % ntn) * BN, 0, q.K, As, Bs);
+  }
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN, bool A_KC, bool B_NC>
@@ -401,6 +441,56 @@ int pick_variant(Context& ctx, int kind, int M, int N, int K, int cls, int nvari
   return best;
 }
 
+// Large products of two row-major operands with 16-byte aligned rows take
+// dgemm_rr.
+static bool rr_eligible(int M, int N, int K, double alpha, View A, View B, double beta,
+                        ViewOut C) {
+  auto aligned = [](const void* p, long long ld) {
+    return ((reinterpret_cast<uintptr_t>(p) & 15) == 0) && (ld % 2 == 0);
+  };
+  const long long i32 = 0x7fffffffLL;
+  const bool fits32 = (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
+                      (long long)M * C.rs + N < i32;
+  return alpha == 1.0 && beta == 0.0 && A.cs == 1 && B.cs == 1 && C.cs == 1 &&
+         aligned(A.p, A.rs) && aligned(B.p, B.rs) && (A.bs % 2 == 0) && (B.bs % 2 == 0) &&
+         fits32 && M >= 384 && N >= 384 && K >= 16;
+}
+
+// K chunks of a dgemm_rr product: three workgroups fit on a CU; K is split
+// when the tiles fill less than one pass and every chunk keeps at least 32 K
+// tiles.
+static int rr_ksplit(const Context& ctx, int M, int N, int K, int batch, int& kchunk) {
+  constexpr int BM = 96, BN = 96, BK = 16;
+  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+  const long long slots = 3LL * ctx.num_cus;
+  int ksplit = 1;
+  if (tiles < slots && K >= 64 * BK) {
+    ksplit = (int)std::min<long long>(slots / tiles, K / (32 * BK));
+    ksplit = std::max(1, std::min(ksplit, 16));
+  }
+  kchunk = K;
+  if (ksplit > 1) {
+    kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
+    ksplit = (K + kchunk - 1) / kchunk;
+  }
+  return ksplit;
+}
+
+bool rr_grouped_ok(const Context& ctx, int M, int N, int K, View A, View B, ViewOut C) {
+  int kchunk = 0;
+  return rr_eligible(M, N, K, 1.0, A, B, 0.0, C) && A.bs == 0 && B.bs == 0 &&
+         rr_ksplit(ctx, M, N, K, 1, kchunk) == 1;
+}
+
+void gemm_grouped_f64(Context& ctx, const GroupTable& tab, int* counter) {
+  if (tab.total <= 0) return;
+  fill_zero_int(ctx, counter, 1);
+  const int grid = (int)std::min<long long>(tab.total, 3LL * ctx.num_cus);
+  hipLaunchKernelGGL((dgemm_rr_grouped<96, 96, 16, 2, 2>), dim3(grid), dim3(256), 0, ctx.stream,
+                     tab, counter);
+  CTM_HIP(hipGetLastError());
+}
+
 void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, double beta,
               ViewOut C, int batch, int cls) {
   CTM_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 1, "gemm: negative size");
@@ -416,33 +506,14 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
     CTM_HIP(hipGetLastError());
     return;
   }
-  // Large products of two row-major operands with 16-byte aligned rows.
-  auto aligned = [](const void* p, long long ld) {
-    return ((reinterpret_cast<uintptr_t>(p) & 15) == 0) && (ld % 2 == 0);
-  };
-  const long long i32 = 0x7fffffffLL;
-  const bool fits32 = (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
-                      (long long)M * C.rs + N < i32;
-  if (alpha == 1.0 && beta == 0.0 && A.cs == 1 && B.cs == 1 && C.cs == 1 &&
-      aligned(A.p, A.rs) && aligned(B.p, B.rs) && (A.bs % 2 == 0) && (B.bs % 2 == 0) && fits32 &&
-      M >= 384 && N >= 384 && K >= 16) {
+  if (rr_eligible(M, N, K, alpha, A, B, beta, C)) {
     constexpr int BM = 96, BN = 96, BK = 16;
+    const long long i32 = 0x7fffffffLL;
     const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
     CTM_REQUIRE(tiles <= i32 && batch <= 65535, "gemm: grid too large");
-    // three workgroups fit on a CU; split K when the tiles fill less than
-    // one pass and every chunk keeps at least 32 K tiles
-    const long long slots = 3LL * ctx.num_cus;
-    int ksplit = 1;
-    if (tiles < slots && K >= 64 * BK) {
-      ksplit = (int)std::min<long long>(slots / tiles, K / (32 * BK));
-      ksplit = std::max(1, std::min(ksplit, 16));
-    }
     int kchunk = K;
+    int ksplit = rr_ksplit(ctx, M, N, K, batch, kchunk);
     double* W = nullptr;
-    if (ksplit > 1) {
-      kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
-      ksplit = (K + kchunk - 1) / kchunk;
-    }
     if (ksplit > 1) {
       const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
       if (ctx.splitk_ws.bytes < need) {

@@ -321,26 +321,21 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
 // C = A B with FP64 operands rounded to FP32 on the way into LDS, FP32 MFMA
 // and FP32 accumulation; same staging as the FP64 row-major kernel (96 x 96
 // tile, 2 x 2 waves, 16-byte global loads, double-buffered LDS).
-template <int BM, int BN, int WGM, int WGN, int TAG>
-__global__ __launch_bounds__(WGM * WGN * 64) void gemm_f32x1_kernel(int M, int N, int K,
-                                                                    const double* __restrict__ A,
-                                                                    int lda,
-                                                                    const double* __restrict__ B,
-                                                                    int ldb,
-                                                                    double* __restrict__ C,
-                                                                    int ldc) {
+// One BM x BN tile of the FP32 product at (m0, n0), for gemm_f32x1_kernel
+// and the grouped kernel.
+template <int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void f32_tile(int M, int N, int K, const double* __restrict__ A, int lda,
+                                         const double* __restrict__ B, int ldb,
+                                         double* __restrict__ C, int ldc, int m0, int n0,
+                                         float (*As)[BM * 17], float (*Bs)[16 * (BN + 1)]) {
   constexpr int BK = 16, NT = WGM * WGN * 64;
   constexpr int WM = BM / WGM, WN = BN / WGN, TI = WM / 16, TJ = WN / 16;
   static_assert(TI * 16 == WM && TJ * 16 == WN, "wave tile must be a multiple of 16");
   static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "pair mapping");
   constexpr int SA = BK + 1, SB = BN + 1;
   constexpr int AV = BM * BK / 2 / NT, BV = BK * BN / 2 / NT;
-  __shared__ float As[2][BM * SA];
-  __shared__ float Bs[2][BK * SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
-  const int ntn = (N + BN - 1) / BN;
-  const int m0 = (blockIdx.x / ntn) * BM, n0 = (blockIdx.x % ntn) * BN;
   const bool full_m = (m0 + BM <= M), full_n = (n0 + BN <= N);
   d2v ra[AV], rb[BV];
   auto load = [&](int kt) {
@@ -426,6 +421,43 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_f32x1_kernel(int M, int N
       }
 }
 
+template <int BM, int BN, int WGM, int WGN, int TAG>
+__global__ __launch_bounds__(WGM * WGN * 64) void gemm_f32x1_kernel(int M, int N, int K,
+                                                                    const double* __restrict__ A,
+                                                                    int lda,
+                                                                    const double* __restrict__ B,
+                                                                    int ldb,
+                                                                    double* __restrict__ C,
+                                                                    int ldc) {
+  __shared__ float As[2][BM * 17];
+  __shared__ float Bs[2][16 * (BN + 1)];
+  const int ntn = (N + BN - 1) / BN;
+  f32_tile<BM, BN, WGM, WGN>(M, N, K, A, lda, B, ldb, C, ldc, (blockIdx.x / ntn) * BM,
+                             (blockIdx.x % ntn) * BN, As, Bs);
+}
+
+// Grouped FP32 products: the persistent tile queue of dgemm_rr_grouped
+// over f32_tile.
+__global__ __launch_bounds__(256) void gemm_f32x1_grouped(GroupTable tab, int* __restrict__ counter) {
+  __shared__ float As[2][96 * 17];
+  __shared__ float Bs[2][16 * 97];
+  __shared__ int claim;
+  for (;;) {
+    if (threadIdx.x == 0) claim = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = claim;
+    __syncthreads();
+    if (t >= tab.total) break;
+    int p = 0;
+    while (p + 1 < tab.count && tab.tile_start[p + 1] <= t) ++p;
+    const GroupProblem& q = tab.p[p];
+    const int local = t - tab.tile_start[p];
+    const int ntn = (q.N + 95) / 96;
+    f32_tile<96, 96, 2, 2>(q.M, q.N, q.K, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, (local / ntn) * 96,
+                           (local % ntn) * 96, As, Bs);
+  }
+}
+
 namespace {
 
 template <int S>
@@ -477,16 +509,55 @@ bool mixed_mode_supported(int mode) {
          mode == CTM_PREC_BF16X4;
 }
 
+// The reduced-precision kernels cover plain row-major products C = A B with
+// 16-byte aligned operands and 32-bit offsets.
+static bool mixed_plain(int mode, int M, int N, int K, double alpha, View A, View B, double beta,
+                        ViewOut C, int batch) {
+  const long long i32 = INT_MAX;
+  return mode != CTM_PREC_F64 && alpha == 1.0 && beta == 0.0 && batch == 1 && A.cs == 1 &&
+         B.cs == 1 && C.cs == 1 && M >= 1 && N >= 1 && K >= 1 && (long long)M * A.rs + K < i32 &&
+         (long long)K * B.rs + N < i32 && (long long)M * C.rs + N < i32 &&
+         ((reinterpret_cast<uintptr_t>(A.p) | reinterpret_cast<uintptr_t>(B.p)) & 15) == 0 &&
+         A.rs % 2 == 0 && B.rs % 2 == 0;
+}
+
+int grouped_kind(const Context& ctx, int mode, int M, int N, int K, View A, View B, ViewOut C) {
+  if (mixed_plain(mode, M, N, K, 1.0, A, B, 0.0, C, 1)) return mode == CTM_PREC_F32 ? 2 : 0;
+  return rr_grouped_ok(ctx, M, N, K, A, B, C) ? 1 : 0;
+}
+
+void gemm_grouped(Context& ctx, int kind, const GroupProblem* probs, int count, int* counter) {
+  CTM_REQUIRE(kind == 1 || kind == 2, "gemm_grouped: unknown kernel kind");
+  for (int s = 0; s < count; s += kGroupMax) {
+    GroupTable tab{};
+    tab.count = std::min(kGroupMax, count - s);
+    long long total = 0;
+    for (int i = 0; i < tab.count; ++i) {
+      const GroupProblem& q = probs[s + i];
+      CTM_REQUIRE(q.M >= 1 && q.N >= 1 && q.K >= 1, "gemm_grouped: empty problem");
+      tab.p[i] = q;
+      tab.tile_start[i] = (int)total;
+      total += (long long)((q.M + 95) / 96) * ((q.N + 95) / 96);
+      CTM_REQUIRE(total < INT_MAX / 2, "gemm_grouped: too many tiles");
+    }
+    tab.tile_start[tab.count] = (int)total;
+    tab.total = (int)total;
+    if (kind == 1) {
+      gemm_grouped_f64(ctx, tab, counter);
+    } else {
+      fill_zero_int(ctx, counter, 1);
+      const int grid = (int)std::min<long long>(total, 3LL * ctx.num_cus);
+      hipLaunchKernelGGL(gemm_f32x1_grouped, dim3(grid), dim3(256), 0, ctx.stream, tab, counter);
+      CTM_HIP(hipGetLastError());
+    }
+  }
+}
+
 void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View A, View B,
                 double beta, ViewOut C, int batch, int cls) {
   CTM_REQUIRE(mixed_mode_supported(mode), "precision mode not available");
   const long long i32 = INT_MAX;
-  const bool plain = mode != CTM_PREC_F64 && alpha == 1.0 && beta == 0.0 && batch == 1 &&
-                     A.cs == 1 && B.cs == 1 && C.cs == 1 && M >= 1 && N >= 1 && K >= 1 &&
-                     (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
-                     (long long)M * C.rs + N < i32 &&
-                     ((reinterpret_cast<uintptr_t>(A.p) | reinterpret_cast<uintptr_t>(B.p)) & 15) == 0 &&
-                     A.rs % 2 == 0 && B.rs % 2 == 0;
+  const bool plain = mixed_plain(mode, M, N, K, alpha, A, B, beta, C, batch);
   if (!plain) {
     // FP64 for every contraction the reduced-precision kernels do not cover
     gemm_f64(ctx, M, N, K, alpha, A, B, beta, C, batch, cls);

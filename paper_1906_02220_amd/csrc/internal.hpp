@@ -168,6 +168,33 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
 // and outputs: FP32 MFMA for CTM_PREC_F32, BF16 slices for CTM_PREC_BF16X*.
 // Products the reduced-precision kernels do not cover (alpha != 1, beta != 0,
 // batched or transposed operands) and CTM_PREC_F64 run as gemm_f64.
+// Grouped products C = A B: independent problems run in one persistent
+// launch whose workgroups claim tiles from a device counter (see
+// dgemm_rr_grouped).  A problem is grouped only where the plain call would
+// run the same tile kernel without split-K, so that grouping never changes
+// a result.
+struct GroupProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K, lda, ldb, ldc;
+};
+constexpr int kGroupMax = 32;
+struct GroupTable {
+  int count, total;
+  int tile_start[kGroupMax + 1];
+  GroupProblem p[kGroupMax];
+};
+// dgemm_rr without split-K would take this product
+bool rr_grouped_ok(const Context& ctx, int M, int N, int K, View A, View B, ViewOut C);
+void gemm_grouped_f64(Context& ctx, const GroupTable& tab, int* counter);
+// 1: the product of `mode` runs on the FP64 96 x 96 kernel, 2: on the FP32
+// 96 x 96 kernel (both without split-K), 0: on neither (it is not grouped)
+int grouped_kind(const Context& ctx, int mode, int M, int N, int K, View A, View B, ViewOut C);
+// all problems of one kind, in launches of at most kGroupMax problems on
+// ctx.stream; counter: one int of device memory
+void gemm_grouped(Context& ctx, int kind, const GroupProblem* probs, int count, int* counter);
+
 void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View A, View B,
                 double beta, ViewOut C, int batch = 1, int cls = -1);
 // Modes gemm_mixed implements.

@@ -87,6 +87,8 @@ SIGNATURES = {
     "ctm_sweep": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _I, _D]),
     "ctm_sweep_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                        ctypes.c_double, _I, _D]),
+    "ctm_sweep_batch_grouped": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_double, _I, _D]),
     "ctm_move": (ctypes.c_int, [_P, ctypes.c_int]),
     "ctm_norm": (ctypes.c_int, [_P, _D]),
     "ctm_log_z": (ctypes.c_int, [_P, _D, _D]),
@@ -225,10 +227,12 @@ class Context:
             pass
 
 
-def sweep_batch(envs, max_sweeps, tol=0.0):
-    """Sweeps of several environments at once (ctm_sweep_batch): environments
-    on different contexts run concurrently.  Returns (rc, sweeps_done, delta)
-    with one entry per environment."""
+def sweep_batch(envs, max_sweeps, tol=0.0, grouped=False):
+    """Sweeps of several environments at once: ctm_sweep_batch (environments
+    on different contexts run concurrently) or, with grouped=True,
+    ctm_sweep_batch_grouped (lock-step moves whose n x n x n products run as
+    grouped launches).  Returns (rc, sweeps_done, delta) with one entry per
+    environment."""
     envs = list(envs)
     n = len(envs)
     if n == 0:
@@ -236,9 +240,11 @@ def sweep_batch(envs, max_sweeps, tol=0.0):
     arr = (_P * n)(*[e.h for e in envs])
     done = np.zeros(n, dtype=np.int32)
     delta = np.zeros(n)
-    rc = load_library().ctm_sweep_batch(arr, n, max_sweeps, tol,
-                                        done.ctypes.data_as(_I), delta.ctypes.data_as(_D))
-    envs[0].ctx.check(rc, "ctm_sweep_batch")
+    lib = load_library()
+    name = "ctm_sweep_batch_grouped" if grouped else "ctm_sweep_batch"
+    rc = getattr(lib, name)(arr, n, max_sweeps, tol, done.ctypes.data_as(_I),
+                            delta.ctypes.data_as(_D))
+    envs[0].ctx.check(rc, name)
     return rc, done, delta
 
 

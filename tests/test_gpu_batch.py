@@ -139,3 +139,66 @@ def test_autotuned_tilings_give_identical_results(mode):
     e1 = _env(c1, 4, 32, 1234, precision=mode)
     assert e0.sweep(6) == e1.sweep(6)
     _same(_state(e0), _state(e1))
+
+
+# (D, chi, seed, gamma, precision): F64 at n = 512 (grouped, FP64 tile
+# kernel), F32 at n = 512 and n = 500 (grouped, FP32 tile kernel), F64 at
+# n = 1152 (split-K in a plain sweep, so not grouped), BF16x3 (not grouped),
+# F64 at n = 180 (generic kernel, not grouped) and D = 2 (direct SVD)
+GROUPED = [(4, 32, 1234, 2, ctm.CTM_PREC_F64), (4, 32, 7, 1, ctm.CTM_PREC_F32),
+           (5, 20, 11, 0, ctm.CTM_PREC_F32), (4, 72, 5, 2, ctm.CTM_PREC_F64),
+           (4, 32, 8, 2, ctm.CTM_PREC_BF16X3), (3, 20, 4, 1, ctm.CTM_PREC_F64),
+           (2, 12, 3, 2, ctm.CTM_PREC_F64)]
+
+
+def test_grouped_batch_matches_sequential():
+    """Lock-step batch with grouped n x n x n products equals plain sweeps
+    bit for bit, for grouped and ungrouped members alike; two members share
+    a context, one context has graphs on (its graph is dropped)."""
+    say("case: grouped batch of %d environments, 6 sweeps" % len(GROUPED))
+    ctxs = [ctm.Context(0) for _ in GROUPED[:-1]]
+    ctxs.append(ctxs[0])
+    ctxs[1].graphs(True)
+    batch = [_env(c, D, chi, seed, gamma, precision=p)
+             for c, (D, chi, seed, gamma, p) in zip(ctxs, GROUPED)]
+    batch[1].sweep(3)  # captures a graph on the graph-enabled context
+    rc, done, delta = ctm.sweep_batch(batch, 6, 0.0, grouped=True)
+    assert rc == ctm.CTM_OK and list(done) == [6] * len(GROUPED)
+    cs = ctm.Context(0)
+    for i, ((D, chi, seed, gamma, p), eb, db) in enumerate(zip(GROUPED, batch, delta)):
+        say("  member %d: D=%d chi=%d precision %d" % (i, D, chi, p))
+        es = _env(cs, D, chi, seed, gamma, precision=p)
+        _, _, dels = es.sweep(9 if i == 1 else 6)
+        assert dels == db
+        _same(_state(eb), _state(es))
+    # graph replay resumes on the member whose graph was dropped
+    es = _env(cs, 4, 32, 7, 1, precision=ctm.CTM_PREC_F32)
+    es.sweep(9)
+    assert batch[1].sweep(3) == es.sweep(3)
+    _same(_state(batch[1]), _state(es))
+
+
+def test_grouped_batch_tolerance_and_errors():
+    say("case: grouped batch with tol, ENOTCONV and a non-finite member")
+    c1, c2 = ctm.Context(0), ctm.Context(0)
+    envs = [_env(c1, 4, 32, 1234), _env(c2, 4, 32, 7, 1)]
+    rc, done, delta = ctm.sweep_batch(envs, 40, 1e-6, grouped=True)
+    say("  rc %d done %s delta %s" % (rc, list(done), list(delta)))
+    # each member stops on its own, exactly where a plain sweep loop stops
+    for (D, chi, seed, gamma), d, dl in zip([(4, 32, 1234, 2), (4, 32, 7, 1)], done, delta):
+        rcs, dr, delr = _env(c1, D, chi, seed, gamma).sweep(40, 1e-6)
+        assert dr == d and delr == dl
+        assert (rcs == ctm.CTM_OK) == (dl < 1e-6)
+    assert (rc == ctm.CTM_OK) == bool(np.all(delta < 1e-6))
+    rc, done, delta = ctm.sweep_batch([_env(c1, 2, 12, 3)], 2, 1e-300, grouped=True)
+    assert rc == ctm.CTM_ENOTCONV and list(done) == [2]
+    A, B = synth.random_purification(4, 1)
+    A = A.copy()
+    A[0, 0, 0, 0, 0] = np.nan
+    bad = ctm.Environment.from_purification(c2, A, B, 2, 32)
+    good = _env(c1, 4, 32, 3)
+    with pytest.raises(ctm.CtmError) as ei:
+        ctm.sweep_batch([good, bad], 3, 0.0, grouped=True)
+    assert ei.value.code == ctm.CTM_ENUMERIC
+    assert "environment 1" in str(ei.value)
+    assert np.isfinite(good.norm())
