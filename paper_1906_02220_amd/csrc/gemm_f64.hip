@@ -42,16 +42,20 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 // Offsets within one matrix are 32-bit (the dispatcher checks that they
 // fit), which keeps the address arithmetic of the loads short.
 //
-// Split-K: blockIdx.z selects the K chunk [z kchunk, (z + 1) kchunk); with
-// ksplit > 1 the chunk's partial product goes to W (row stride N, one M x N
-// slab per (batch, chunk)) for the fixed-order reduction.
+// Split-K: blockIdx.z selects the K chunk [z kchunk, (z + 1) kchunk).  With
+// a workspace W (ksplit > 1, or a product with alpha != 1, beta != 0 or a
+// strided C) each chunk's partial product goes to W (row stride N, one M x N
+// slab per (batch, chunk)) for the fixed-order reduction, which also applies
+// alpha and beta.
 // One BM x BN tile of C = A B at (m0, n0) over the K range [kbeg, kend),
-// for dgemm_rr and the grouped kernel: 16-byte global loads into registers,
+// for dgemm_rr and the grouped kernel: 16-byte global loads into registers
+// (two 8-byte loads for an operand whose rows are not 16-byte aligned, VA /
+// VB false),
 // A staged [m][k] and B [k][n] in double-buffered LDS (one barrier per K
 // tile), and a plain store of the accumulators.  An alpha / beta epilogue
 // here costs enough registers to drop the occupancy to two workgroups per
 // CU, so the dispatchers send only C = A B products to it.
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int BM, int BN, int BK, int WGM, int WGN, bool VA = true, bool VB = true>
 __device__ __forceinline__ void rr_tile(int M, int N, const double* __restrict__ A, int lda,
                                         const double* __restrict__ B, int ldb,
                                         double* __restrict__ C, int ldc, int m0, int n0, int kbeg,
@@ -77,7 +81,7 @@ __device__ __forceinline__ void rr_tile(int M, int N, const double* __restrict__
       const int p = tid + e * NT;
       const int r = p / (BK / 2), k = (p % (BK / 2)) * 2;
       const int gm = m0 + r, gk = kt + k;
-      if ((full_m || gm < M) && gk + 1 < kend) {
+      if (VA && (full_m || gm < M) && gk + 1 < kend) {
         ra[e] = *(const d2v*)(A + gm * lda + gk);
       } else {
         ra[e].x = (gm < M && gk < kend) ? A[gm * lda + gk] : 0.0;
@@ -89,7 +93,7 @@ __device__ __forceinline__ void rr_tile(int M, int N, const double* __restrict__
       const int p = tid + e * NT;
       const int k = p / (BN / 2), c = (p % (BN / 2)) * 2;
       const int gk = kt + k, gn = n0 + c;
-      if (gk < kend && (full_n || gn + 1 < N)) {
+      if (VB && gk < kend && (full_n || gn + 1 < N)) {
         rb[e] = *(const d2v*)(B + gk * ldb + gn);
       } else {
         rb[e].x = (gk < kend && gn < N) ? B[gk * ldb + gn] : 0.0;
@@ -151,7 +155,7 @@ __device__ __forceinline__ void rr_tile(int M, int N, const double* __restrict__
       }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int TAG>
+template <int BM, int BN, int BK, int WGM, int WGN, int TAG, bool VA = true, bool VB = true>
 __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
     int M, int N, int K, const double* __restrict__ A, int lda, long long abs_,
     const double* __restrict__ B, int ldb, long long bbs, double* __restrict__ C, int ldc,
@@ -162,15 +166,15 @@ __global__ __launch_bounds__(WGM * WGN * 64) void dgemm_rr(
   xcd_tile<8>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
   A += blockIdx.y * abs_;
   B += blockIdx.y * bbs;
-  if (ksplit > 1) {
+  if (W) {
     C = W + ((long long)blockIdx.y * ksplit + blockIdx.z) * ((long long)M * N);
     ldc = N;
   } else {
     C += blockIdx.y * cbs;
   }
   const int kbeg = blockIdx.z * kchunk;
-  rr_tile<BM, BN, BK, WGM, WGN>(M, N, A, lda, B, ldb, C, ldc, tm * BM, tn * BN, kbeg,
-                                min(K, kbeg + kchunk), As, Bs);
+  rr_tile<BM, BN, BK, WGM, WGN, VA, VB>(M, N, A, lda, B, ldb, C, ldc, tm * BM, tn * BN, kbeg,
+                                        min(K, kbeg + kchunk), As, Bs);
 }
 
 // Grouped products: one persistent launch over a table of independent
@@ -441,19 +445,23 @@ int pick_variant(Context& ctx, int kind, int M, int N, int K, int cls, int nvari
   return best;
 }
 
-// Large products of two row-major operands with 16-byte aligned rows take
-// dgemm_rr.
-static bool rr_eligible(int M, int N, int K, double alpha, View A, View B, double beta,
-                        ViewOut C) {
-  auto aligned = [](const void* p, long long ld) {
-    return ((reinterpret_cast<uintptr_t>(p) & 15) == 0) && (ld % 2 == 0);
-  };
+// Large products of two row-major operands take dgemm_rr.
+static bool rr_eligible(int M, int N, int K, View A, View B) {
   const long long i32 = 0x7fffffffLL;
   const bool fits32 = (long long)M * A.rs + K < i32 && (long long)K * B.rs + N < i32 &&
-                      (long long)M * C.rs + N < i32;
-  return alpha == 1.0 && beta == 0.0 && A.cs == 1 && B.cs == 1 && C.cs == 1 &&
-         aligned(A.p, A.rs) && aligned(B.p, B.rs) && (A.bs % 2 == 0) && (B.bs % 2 == 0) &&
-         fits32 && M >= 384 && N >= 384 && K >= 16;
+                      (long long)M * N < i32;
+  return A.cs == 1 && B.cs == 1 && fits32 && M >= 384 && N >= 384 && K >= 16;
+}
+
+// dgemm_rr writes C itself (otherwise through the split-K workspace).
+static bool rr_direct(int M, int N, double alpha, double beta, ViewOut C) {
+  return alpha == 1.0 && beta == 0.0 && C.cs == 1 && (long long)M * C.rs + N < 0x7fffffffLL;
+}
+
+// Every row of every batch entry starts 16-byte aligned: the operand takes
+// 16-byte loads.
+static bool rr_vec(const View& X) {
+  return ((reinterpret_cast<uintptr_t>(X.p) & 15) == 0) && (X.rs % 2 == 0) && (X.bs % 2 == 0);
 }
 
 // K chunks of a dgemm_rr product: three workgroups fit on a CU; K is split
@@ -478,8 +486,8 @@ static int rr_ksplit(const Context& ctx, int M, int N, int K, int batch, int& kc
 
 bool rr_grouped_ok(const Context& ctx, int M, int N, int K, View A, View B, ViewOut C) {
   int kchunk = 0;
-  return rr_eligible(M, N, K, 1.0, A, B, 0.0, C) && A.bs == 0 && B.bs == 0 &&
-         rr_ksplit(ctx, M, N, K, 1, kchunk) == 1;
+  return rr_eligible(M, N, K, A, B) && rr_direct(M, N, 1.0, 0.0, C) && rr_vec(A) && rr_vec(B) &&
+         A.bs == 0 && B.bs == 0 && rr_ksplit(ctx, M, N, K, 1, kchunk) == 1;
 }
 
 void gemm_grouped_f64(Context& ctx, const GroupTable& tab, int* counter) {
@@ -506,15 +514,16 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
     CTM_HIP(hipGetLastError());
     return;
   }
-  if (rr_eligible(M, N, K, alpha, A, B, beta, C)) {
+  if (rr_eligible(M, N, K, A, B)) {
     constexpr int BM = 96, BN = 96, BK = 16;
     const long long i32 = 0x7fffffffLL;
     const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
     CTM_REQUIRE(tiles <= i32 && batch <= 65535, "gemm: grid too large");
     int kchunk = K;
     int ksplit = rr_ksplit(ctx, M, N, K, batch, kchunk);
+    const bool direct = rr_direct(M, N, alpha, beta, C);
     double* W = nullptr;
-    if (ksplit > 1) {
+    if (ksplit > 1 || !direct) {
       const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
       if (ctx.splitk_ws.bytes < need) {
         CTM_HIP(hipStreamSynchronize(ctx.stream));
@@ -523,7 +532,8 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
       W = ctx.splitk_ws.d();
     }
     const int lda = (int)A.rs, ldb = (int)B.rs, ldc = (int)C.rs;
-    if (ksplit == 1 && ctx.autotune) {
+    const bool va = rr_vec(A), vb = rr_vec(B);
+    if (ksplit == 1 && direct && ctx.autotune && va && vb) {
       // tile candidates: 96 x 96 (2 x 2 waves), 128 x 128 (4 x 2), 64 x 64 (2 x 2);
       // all accumulate K in the same order, so the choice never changes C
       auto run = [&](int v) {
@@ -550,18 +560,29 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
       return;
     }
     const dim3 grid((unsigned)(tiles / batch), batch, ksplit), block(256);
-    if (cls == 0)
-      hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, 0>), grid, block, 0, ctx.stream, M, N, K,
-                         A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W);
-    else
-      hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, 1>), grid, block, 0, ctx.stream, M, N, K,
-                         A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W);
+#define CTM_RRV(TAG_, VA_, VB_)                                                                 \
+  hipLaunchKernelGGL((dgemm_rr<BM, BN, BK, 2, 2, TAG_, VA_, VB_>), grid, block, 0, ctx.stream, M, N, \
+                     K, A.p, lda, A.bs, B.p, ldb, B.bs, C.p, ldc, C.bs, ksplit, kchunk, W)
+    const int tag = cls == 0 ? 0 : 1;
+    const int v = (va ? 2 : 0) + (vb ? 1 : 0);
+    if (tag == 0) {
+      if (v == 3) CTM_RRV(0, true, true);
+      else if (v == 2) CTM_RRV(0, true, false);
+      else if (v == 1) CTM_RRV(0, false, true);
+      else CTM_RRV(0, false, false);
+    } else {
+      if (v == 3) CTM_RRV(1, true, true);
+      else if (v == 2) CTM_RRV(1, true, false);
+      else if (v == 1) CTM_RRV(1, false, true);
+      else CTM_RRV(1, false, false);
+    }
+#undef CTM_RRV
     CTM_HIP(hipGetLastError());
-    if (ksplit > 1) {
+    if (W) {
       const long long total = (long long)M * N * batch;
       const int blocks = (int)std::min<long long>((total + 255) / 256, 8192);
       hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, ctx.stream, M, N,
-                         ksplit, batch, 1.0, W, 0.0, C.p, C.rs, C.cs, C.bs);
+                         ksplit, batch, alpha, W, beta, C.p, C.rs, C.cs, C.bs);
       CTM_HIP(hipGetLastError());
     }
     return;
