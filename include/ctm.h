@@ -130,6 +130,19 @@ int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi,
 int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B,
                               int D, int D_gamma, int gamma, int chi,
                               const ctm_opts* opts, ctm_env** out);
+
+/* The same two constructors with the tensors in device memory (for example
+ * torch-owned): a, A and B are device pointers on the context's device, in
+ * the layouts above.  They are read by kernels on the context's stream
+ * (ctm_context_set_stream), so the caller makes them ready there first; the
+ * library does not keep them after the call returns.  Returns CTM_EINVAL if
+ * a pointer is not device (or managed) memory of that device or the
+ * allocation it lies in ends before the tensor does. */
+int ctm_env_init_tensor_dev(ctm_context* ctx, const double* a, int d, int chi,
+                            const ctm_opts* opts, ctm_env** out);
+int ctm_env_init_purification_dev(ctm_context* ctx, const double* A, const double* B,
+                                  int D, int D_gamma, int gamma, int chi,
+                                  const ctm_opts* opts, ctm_env** out);
 void ctm_env_destroy(ctm_env* env);
 
 /* CTMRG sweeps (Fig. 4(c)).  One sweep is the left, right, up and down

@@ -192,33 +192,68 @@ int ctm_context_set_graphs(ctm_context* ctx, int on) {
   return guarded(ctx, [&] { ctx->c.use_graphs = (on != 0); });
 }
 
-int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
-                        ctm_env** out) {
+// A caller's device array: p must lie in one device allocation of the
+// context's device (or managed memory) that holds `bytes` from p on.
+static void check_device_array(const ctm::Context& c, const void* p, size_t bytes,
+                               const char* what) {
+  hipPointerAttribute_t attr{};
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) (void)hipGetLastError();
+  const bool dev = e == hipSuccess && (attr.type == hipMemoryTypeDevice ||
+                                       attr.type == hipMemoryTypeManaged);
+  CTM_REQUIRE(dev, std::string(what) + " is not device memory");
+  CTM_REQUIRE(attr.type == hipMemoryTypeManaged || attr.device == c.device,
+              std::string(what) + " lives on another device than the context's");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    CTM_REQUIRE(false, std::string(what) + ": allocation range unknown");
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  CTM_REQUIRE(q >= b && (size_t)(q - b) + bytes <= size,
+              std::string(what) + " is shorter than the tensor it should hold");
+}
+
+static ctm_env* new_env(ctm_context* ctx, int d, int chi, const ctm_opts* opts) {
+  ctm::EnvOptions o = to_options(opts, d);
+  check_precision(o.precision);
+  CTM_HIP(hipSetDevice(ctx->c.device));
+  auto env = std::make_unique<ctm_env>();
+  env->owner_sp = ctx->sp;
+  env->owner_c = ctx->sp.get();
+  env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
+  return env.release();
+}
+
+static int init_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                       ctm_env** out, bool on_device) {
   if (!ctx) return CTM_EINVAL;
   return guarded(ctx, [&] {
     CTM_REQUIRE(a && out, "null argument");
     CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
     *out = nullptr;
-    ctm::EnvOptions o = to_options(opts, d);
-    check_precision(o.precision);
-    CTM_HIP(hipSetDevice(ctx->c.device));
-    auto env = std::make_unique<ctm_env>();
-    env->owner_sp = ctx->sp;
-    env->owner_c = ctx->sp.get();
-    env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
     const size_t d4 = (size_t)d * d * d * d;
-    ctm::DevBuf da(d4 * sizeof(double));
-    CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
-    env->e->set_site_tensor_dev(da.d());
+    if (on_device) check_device_array(ctx->c, a, d4 * sizeof(double), "a");
+    std::unique_ptr<ctm_env> env(new_env(ctx, d, chi, opts));
+    ctm::DevBuf da;
+    const double* src = a;
+    if (!on_device) {
+      da.alloc(d4 * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      src = da.d();
+    }
+    env->e->set_site_tensor_dev(src);
     env->e->init_boundary();
     CTM_HIP(hipStreamSynchronize(ctx->c.stream));
     *out = env.release();
   });
 }
 
-int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B, int D,
-                              int D_gamma, int gamma, int chi, const ctm_opts* opts,
-                              ctm_env** out) {
+static int init_purification(ctm_context* ctx, const double* A, const double* B, int D,
+                             int D_gamma, int gamma, int chi, const ctm_opts* opts, ctm_env** out,
+                             bool on_device) {
   if (!ctx) return CTM_EINVAL;
   return guarded(ctx, [&] {
     CTM_REQUIRE(A && B && out, "null argument");
@@ -226,23 +261,49 @@ int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B
     CTM_REQUIRE(gamma >= 0 && gamma <= 2, "gamma must be 0, 1 or 2");
     CTM_REQUIRE(D <= 16, "D above 16 is not supported");
     *out = nullptr;
-    const int d = D * D;
-    ctm::EnvOptions o = to_options(opts, d);
-    check_precision(o.precision);
-    CTM_HIP(hipSetDevice(ctx->c.device));
-    auto env = std::make_unique<ctm_env>();
-    env->owner_sp = ctx->sp;
-    env->owner_c = ctx->sp.get();
-    env->e = std::make_unique<ctm::Env>(ctx->c, d, chi, o);
     const size_t sz = 4ull * D * D * D_gamma;
-    ctm::DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double));
-    CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
-    CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
-    env->e->build_purification_dev(dA.d(), dB.d(), D, D_gamma, gamma);
+    if (on_device) {
+      check_device_array(ctx->c, A, sz * sizeof(double), "A");
+      check_device_array(ctx->c, B, sz * sizeof(double), "B");
+    }
+    std::unique_ptr<ctm_env> env(new_env(ctx, D * D, chi, opts));
+    ctm::DevBuf dA, dB;
+    const double *sA = A, *sB = B;
+    if (!on_device) {
+      dA.alloc(sz * sizeof(double));
+      dB.alloc(sz * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      sA = dA.d();
+      sB = dB.d();
+    }
+    env->e->build_purification_dev(sA, sB, D, D_gamma, gamma);
     env->e->init_boundary();
     CTM_HIP(hipStreamSynchronize(ctx->c.stream));
     *out = env.release();
   });
+}
+
+int ctm_env_init_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                        ctm_env** out) {
+  return init_tensor(ctx, a, d, chi, opts, out, false);
+}
+
+int ctm_env_init_tensor_dev(ctm_context* ctx, const double* a, int d, int chi,
+                            const ctm_opts* opts, ctm_env** out) {
+  return init_tensor(ctx, a, d, chi, opts, out, true);
+}
+
+int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B, int D,
+                              int D_gamma, int gamma, int chi, const ctm_opts* opts,
+                              ctm_env** out) {
+  return init_purification(ctx, A, B, D, D_gamma, gamma, chi, opts, out, false);
+}
+
+int ctm_env_init_purification_dev(ctm_context* ctx, const double* A, const double* B, int D,
+                                  int D_gamma, int gamma, int chi, const ctm_opts* opts,
+                                  ctm_env** out) {
+  return init_purification(ctx, A, B, D, D_gamma, gamma, chi, opts, out, true);
 }
 
 void ctm_env_destroy(ctm_env* env) {

@@ -83,6 +83,11 @@ SIGNATURES = {
     "ctm_env_init_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_int,
                                                  ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
+    "ctm_env_init_tensor_dev": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
+    "ctm_env_init_purification_dev": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int,
+                                                     ctypes.c_int, ctypes.c_int,
+                                                     ctypes.POINTER(ctm_opts), ctypes.POINTER(_P)]),
     "ctm_env_destroy": (None, [_P]),
     "ctm_sweep": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, _I, _D]),
     "ctm_sweep_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
@@ -149,6 +154,20 @@ def _dptr(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _on_gpu(x):
+    """A torch tensor in GPU memory (checked without importing torch)."""
+    return bool(getattr(x, "is_cuda", False))
+
+
+def _gpu_f64(x):
+    """Contiguous FP64 copy (or x itself) of a GPU tensor, with the producing
+    stream drained so that the library's stream may read it."""
+    import torch
+    y = x.detach().to(dtype=torch.float64).contiguous()
+    torch.cuda.current_stream(y.device).synchronize()
+    return y
 
 
 def _module_fn(name):
@@ -370,21 +389,33 @@ class Environment:
 
     @classmethod
     def from_tensor(cls, ctx, a, chi, boundary=None, **kw):
-        a = _f64(a)
+        """a: (d, d, d, d) array, or a torch tensor on the GPU (read in place
+        through ctm_env_init_tensor_dev)."""
+        dev = _on_gpu(a)
+        a = _gpu_f64(a) if dev else _f64(a)
         d = a.shape[0]
-        if a.shape != (d, d, d, d):
+        if tuple(a.shape) != (d, d, d, d):
             raise ValueError("a must have shape (d, d, d, d)")
         o, keep = cls._opts(boundary, kw)
         h = _P()
-        ctx.check(ctx.lib.ctm_env_init_tensor(ctx.h, _dptr(a), d, chi, ctypes.byref(o),
-                                              ctypes.byref(h)), "ctm_env_init_tensor")
+        if dev:
+            rc = ctx.lib.ctm_env_init_tensor_dev(ctx.h, _P(a.data_ptr()), d, chi, ctypes.byref(o),
+                                                 ctypes.byref(h))
+            ctx.check(rc, "ctm_env_init_tensor_dev")
+        else:
+            ctx.check(ctx.lib.ctm_env_init_tensor(ctx.h, _dptr(a), d, chi, ctypes.byref(o),
+                                                  ctypes.byref(h)), "ctm_env_init_tensor")
         return cls(ctx, h, keep)
 
     @classmethod
     def from_purification(cls, ctx, A, B, gamma, chi, boundary=None, **kw):
-        A = _f64(A)
-        B = _f64(B)
-        if A.shape != B.shape or A.ndim != 5 or A.shape[:2] != (2, 2):
+        """A, B: (2, 2, Dx, Dy, Dz) arrays, or torch tensors on the GPU (read in
+        place through ctm_env_init_purification_dev)."""
+        dev = _on_gpu(A)
+        if dev != _on_gpu(B):
+            raise ValueError("A and B must both be host arrays or both GPU tensors")
+        A, B = (_gpu_f64(A), _gpu_f64(B)) if dev else (_f64(A), _f64(B))
+        if tuple(A.shape) != tuple(B.shape) or A.ndim != 5 or tuple(A.shape[:2]) != (2, 2):
             raise ValueError("A and B must both have shape (2, 2, Dx, Dy, Dz)")
         if gamma not in (0, 1, 2):
             raise ValueError("gamma must be 0 (x), 1 (y) or 2 (z)")
@@ -395,9 +426,16 @@ class Environment:
             raise ValueError("the two non-fused bonds must share one dimension D")
         o, keep = cls._opts(boundary, kw)
         h = _P()
-        ctx.check(ctx.lib.ctm_env_init_purification(ctx.h, _dptr(A), _dptr(B), rest[0], Dg, gamma,
-                                                    chi, ctypes.byref(o), ctypes.byref(h)),
-                  "ctm_env_init_purification")
+        if dev:
+            rc = ctx.lib.ctm_env_init_purification_dev(ctx.h, _P(A.data_ptr()), _P(B.data_ptr()),
+                                                       rest[0], Dg, gamma, chi, ctypes.byref(o),
+                                                       ctypes.byref(h))
+            ctx.check(rc, "ctm_env_init_purification_dev")
+        else:
+            ctx.check(ctx.lib.ctm_env_init_purification(ctx.h, _dptr(A), _dptr(B), rest[0], Dg,
+                                                        gamma, chi, ctypes.byref(o),
+                                                        ctypes.byref(h)),
+                      "ctm_env_init_purification")
         return cls(ctx, h, keep)
 
     def sweep(self, max_sweeps, tol=0.0):
