@@ -202,3 +202,20 @@ def test_grouped_batch_tolerance_and_errors():
     assert ei.value.code == ctm.CTM_ENUMERIC
     assert "environment 1" in str(ei.value)
     assert np.isfinite(good.norm())
+
+
+def test_grouped_batch_splits_large_groups():
+    """20 FP32 environments at n = 512: 40 half-system products per phase,
+    more than one grouped launch holds (32), still equal to plain sweeps."""
+    say("case: grouped batch of 20 environments (two grouped launches per phase)")
+    ctxs = [ctm.Context(0) for _ in range(20)]
+    batch = [_env(c, 4, 32, 500 + i, gamma=i % 3, precision=ctm.CTM_PREC_F32)
+             for i, c in enumerate(ctxs)]
+    rc, done, delta = ctm.sweep_batch(batch, 3, 0.0, grouped=True)
+    assert rc == ctm.CTM_OK and list(done) == [3] * 20
+    cs = ctm.Context(0)
+    for i in (0, 7, 19):
+        es = _env(cs, 4, 32, 500 + i, gamma=i % 3, precision=ctm.CTM_PREC_F32)
+        _, _, dels = es.sweep(3)
+        assert dels == delta[i]
+        _same(_state(batch[i]), _state(es))
