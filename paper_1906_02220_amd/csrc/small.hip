@@ -186,6 +186,7 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
                                                            int* __restrict__ dep, int* err) {
   constexpr int NR = 96 / TG;
   static_assert(NR * TG == 96, "the thread grid must tile 96");
+  static_assert(TG * TG >= 96, "threads 0..95 load the diagonal scales");
   __shared__ double Dn[96];
   __shared__ double rowk[2][96];
   __shared__ double xrow[2][96];
