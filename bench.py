@@ -150,7 +150,7 @@ PRECISION_TEXT = {
 }
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 3: 2500.0, 4: 2500.0}
 SLICE_PRODUCTS = {0: 1, 1: 1, 3: 6, 4: 10}
-KERNEL_NAMES = {0: "dgemm_rr<96,96,16,2,2,0>", 1: "gemm_f32x1_kernel<0>",
+KERNEL_NAMES = {0: "dgemm_rr<96,96,16,2,2,0,true,true>", 1: "gemm_f32x1_kernel<0>",
                 3: "gemm_bf16s_kernel<3,0,8>", 4: "gemm_bf16s_kernel<4,0,8>"}
 
 
