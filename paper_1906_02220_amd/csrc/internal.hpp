@@ -238,8 +238,6 @@ void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* 
 void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
                     unsigned long long seed, const unsigned long long* counter_in,
                     unsigned long long* counter_out);
-// Scale every column of an n x b row-major Z to unit 2-norm.
-void normalise_columns(Context& ctx, double* Z, int ldz, int n, int b);
 // One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T,
 // singular values sorted descending.  X and Y (b x b row-major) may be null
 // when only the values are wanted.  batch matrices at stride bstride.  With

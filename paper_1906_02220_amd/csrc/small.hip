@@ -301,22 +301,6 @@ __global__ void refill_kernel(double* Q, int ldq, int n, int b, const int* __res
   }
 }
 
-// Scale every column of an n x b row-major Z to unit 2-norm (one block per
-// column, zero columns left as they are).
-__global__ void normalise_cols_kernel(double* Z, int ldz, int n) {
-  __shared__ double sh[256];
-  const int j = blockIdx.x;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double v = Z[(long long)i * ldz + j];
-    s += v * v;
-  }
-  s = block_sum256(s, sh);
-  const double f = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-  if (s > 0.0)
-    for (int i = threadIdx.x; i < n; i += blockDim.x) Z[(long long)i * ldz + j] *= f;
-}
-
 // ------------------------------------------------------------ Jacobi SVD
 
 // Sum over a group of 8 consecutive lanes (half a DPP row): butterflies
@@ -734,11 +718,6 @@ void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* d
   const size_t total = (size_t)n * b;
   hipLaunchKernelGGL(refill_kernel, dim3(grid_for(total, 256, 1024)), dim3(256), 0, ctx.stream, Q,
                      ldq, n, b, dep, seed, counter_in, counter_out);
-  CTM_HIP(hipGetLastError());
-}
-
-void normalise_columns(Context& ctx, double* Z, int ldz, int n, int b) {
-  hipLaunchKernelGGL(normalise_cols_kernel, dim3(b), dim3(256), 0, ctx.stream, Z, ldz, n);
   CTM_HIP(hipGetLastError());
 }
 
