@@ -219,3 +219,23 @@ def test_grouped_batch_splits_large_groups():
         _, _, dels = es.sweep(3)
         assert dels == delta[i]
         _same(_state(batch[i]), _state(es))
+
+
+def test_batch_argument_errors():
+    """Empty batches are a no-op; null members, repeated members and negative
+    counts are refused without touching any environment."""
+    say("case: batch argument errors")
+    c = ctm.Context(0)
+    e = _env(c, 2, 12, 3)
+    lib = ctm.load_library()
+    for name in ("ctm_sweep_batch", "ctm_sweep_batch_grouped"):
+        fn = getattr(lib, name)
+        assert fn((ctm._P * 1)(), 0, 3, 0.0, None, None) == ctm.CTM_OK
+        assert fn((ctm._P * 1)(None), 1, 3, 0.0, None, None) == ctm.CTM_EINVAL
+        arr = (ctm._P * 2)(e.h, e.h)
+        assert fn(arr, 2, 3, 0.0, None, None) == ctm.CTM_EINVAL
+        assert "twice" in lib.ctm_last_error(c.h).decode()
+        assert fn((ctm._P * 1)(e.h), -1, 3, 0.0, None, None) == ctm.CTM_EINVAL
+        assert fn((ctm._P * 1)(e.h), 1, -2, 0.0, None, None) == ctm.CTM_EINVAL
+    # the environment is untouched and still sweeps
+    assert e.sweep(2)[0] == ctm.CTM_OK

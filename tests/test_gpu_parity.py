@@ -111,6 +111,38 @@ def test_honeycomb_padded_gauged_subspace_path(ctx):
     assert abs(env.expect(zz) - CF.honeycomb_bond_correlation(K, K, K, which=2)) < 1e-9
 
 
+@pytest.mark.parametrize("mode", [ctm.CTM_PREC_F64, ctm.CTM_PREC_BF16X3])
+def test_maximum_size_padded_gauged(ctx, mode):
+    """The largest supported shape: D = 7 (d = 49) and chi = 96, so the cut
+    matrix is n = 4704 (49 full 96-wide FP64 tiles, 36.75 128-wide slice
+    tiles) and the subspace SVD runs at its maximum block b = chi = 96.  The
+    honeycomb Ising state padded from D = 2 and gauged on every bond is the
+    same state, so kappa and <sigma sigma> still equal Houtappel's closed
+    forms."""
+    say("case: maximum size D=7 chi=96 (n=4704) precision mode %d" % mode)
+    K = 0.4
+    A, B = synth.honeycomb_ising_tensors(K, K, K)
+    A, B = synth.pad_and_gauge(A, B, 7, seed=31)
+    env = ctm.Environment.from_purification(ctx, A, B, 2, 96, precision=mode)
+    assert env.chi * env.d == 4704
+    env.sweep(12, 0.0)
+    lk = np.log(env.norm())
+    zz = np.kron(synth.SZ, synth.SZ) * 4.0
+    e = env.expect(zz)
+    say("  ln kappa err %.2e  <ss> err %.2e" % (abs(lk - 2.0 * CF.honeycomb_minus_beta_f(K, K, K)),
+                                               abs(e - CF.honeycomb_bond_correlation(K, K, K, which=2))))
+    # A padded state keeps most cut singular values at rounding level, and the
+    # slice products' rounding moves <O> of such a state at the 1e-7 level
+    # (1.2e-7 measured here; the padded D = 6 honeycomb state of the benchmark
+    # shows up to 3e-6), while kappa stays at 1e-12.
+    tol_k = 1e-9 if mode == ctm.CTM_PREC_F64 else 1e-7
+    tol_o = 1e-9 if mode == ctm.CTM_PREC_F64 else 1e-6
+    assert abs(lk - 2.0 * CF.honeycomb_minus_beta_f(K, K, K)) < tol_k
+    assert abs(e - CF.honeycomb_bond_correlation(K, K, K, which=2)) < tol_o
+    sp = env.corner_spectra().reshape(4, 96)
+    assert np.all(np.isfinite(sp)) and np.all(np.diff(sp, axis=1) <= 1e-15)
+
+
 def test_singlets_and_single_gate(ctx):
     say("case: singlets and one gate layer")
     A, B = synth.singlet_tensors()
