@@ -143,6 +143,29 @@ def test_maximum_size_padded_gauged(ctx, mode):
     assert np.all(np.isfinite(sp)) and np.all(np.diff(sp, axis=1) <= 1e-15)
 
 
+@pytest.mark.parametrize("D,chi", [(1, 1), (1, 3), (2, 1), (2, 2)])
+def test_degenerate_shapes(ctx, D, chi):
+    """D = 1 is a product state: kappa = |A|^2 |B|^2 and <H_bond> is the
+    two-site expectation value, for any chi.  chi = 1 and 2 give rank-one
+    and rank-two projectors on the direct-SVD path.  All against the oracle."""
+    say("case: degenerate shape D=%d chi=%d" % (D, chi))
+    A, B = synth.random_purification(D, 21)
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    env = ctm.Environment.from_purification(ctx, A, B, 2, chi)
+    env.sweep(6, 0.0)
+    k_g, e_g = env.norm(), env.expect(H)
+    oenv, a, Kc, _, _ = O.environment_from_purification(A, B, 2, chi, 6)
+    k_o = O.kappa(oenv, a)
+    e_o = O.expect(oenv, a, O.double_layer(Kc, O.full_operator(H, 4)))
+    assert abs(k_g / k_o - 1.0) < 1e-12
+    assert abs(e_g - e_o) < 1e-12
+    if D == 1:
+        psi = np.einsum("sa,tc->satc", A[:, :, 0, 0, 0], B[:, :, 0, 0, 0])
+        e_two = np.einsum("satc,stuv,uavc->", psi, H.reshape(2, 2, 2, 2), psi) / np.sum(psi ** 2)
+        assert abs(k_g / (np.sum(A ** 2) * np.sum(B ** 2)) - 1.0) < 1e-13
+        assert abs(e_g - e_two) < 1e-13
+
+
 def test_singlets_and_single_gate(ctx):
     say("case: singlets and one gate layer")
     A, B = synth.singlet_tensors()
