@@ -336,6 +336,12 @@ int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol,
   std::vector<double> dl(count, INFINITY);
   ctm::Context* errc = envs[0]->owner_c;
   int cur = -1;
+  auto drain_all = [&] {
+    for (int i = 0; i < count; ++i) {
+      (void)hipSetDevice(envs[i]->owner_c->device);
+      (void)hipStreamSynchronize(envs[i]->owner_c->stream);
+    }
+  };
   const int rc = guarded_c(errc, [&] {
     CTM_REQUIRE(max_sweeps >= 0, "max_sweeps must be >= 0");
     for (int i = 0; i < count; ++i)
@@ -368,11 +374,11 @@ int ctm_sweep_batch(ctm_env* const* envs, int count, int max_sweeps, double tol,
       }
     } catch (const ctm::Error& e) {
       // drain every stream before reporting, so that no work is left in flight
-      for (int i = 0; i < count; ++i) {
-        (void)hipSetDevice(envs[i]->owner_c->device);
-        (void)hipStreamSynchronize(envs[i]->owner_c->stream);
-      }
+      drain_all();
       throw ctm::Error(e.code, "environment " + std::to_string(cur) + ": " + e.what());
+    } catch (...) {
+      drain_all();
+      throw;
     }
   });
   for (int i = 0; i < count; ++i) {
@@ -572,6 +578,13 @@ int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, dou
     for (int i = 0; i < count; ++i) (void)hipStreamSynchronize(envs[i]->owner_c->stream);
     if (grp.stream) (void)hipStreamSynchronize(grp.stream);
   };
+  auto destroy_events = [&] {
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (evg) (void)hipEventDestroy(evg);
+    std::fill(ev.begin(), ev.end(), nullptr);
+    evg = nullptr;
+  };
   const int rc = guarded_c(gc, [&] {
     CTM_REQUIRE(max_sweeps >= 0, "max_sweeps must be >= 0");
     for (int i = 0; i < count; ++i) {
@@ -649,15 +662,15 @@ int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, dou
       drain();
     } catch (const ctm::Error& e) {
       drain();
-      for (auto& x : ev)
-        if (x) (void)hipEventDestroy(x);
-      if (evg) (void)hipEventDestroy(evg);
+      destroy_events();
       throw ctm::Error(e.code, cur >= 0 ? "environment " + std::to_string(cur) + ": " + e.what()
                                         : std::string(e.what()));
+    } catch (...) {
+      drain();
+      destroy_events();
+      throw;
     }
-    for (auto& x : ev)
-      if (x) (void)hipEventDestroy(x);
-    if (evg) (void)hipEventDestroy(evg);
+    destroy_events();
   });
   for (int i = 0; i < count; ++i) {
     if (sweeps_done) sweeps_done[i] = done[i];
