@@ -136,8 +136,8 @@ int ctm_env_init_purification(ctm_context* ctx, const double* A, const double* B
  * the layouts above.  They are read by kernels on the context's stream
  * (ctm_context_set_stream), so the caller makes them ready there first; the
  * library does not keep them after the call returns.  Returns CTM_EINVAL if
- * a pointer is not device (or managed) memory of that device or the
- * allocation it lies in ends before the tensor does. */
+ * a pointer is not device memory (hipMalloc-type, not host or managed) of
+ * that device or the allocation it lies in ends before the tensor does. */
 int ctm_env_init_tensor_dev(ctm_context* ctx, const double* a, int d, int chi,
                             const ctm_opts* opts, ctm_env** out);
 int ctm_env_init_purification_dev(ctm_context* ctx, const double* A, const double* B,

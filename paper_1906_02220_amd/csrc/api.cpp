@@ -193,16 +193,15 @@ int ctm_context_set_graphs(ctm_context* ctx, int on) {
 }
 
 // A caller's device array: p must lie in one device allocation of the
-// context's device (or managed memory) that holds `bytes` from p on.
+// context's device that holds `bytes` from p on.
 static void check_device_array(const ctm::Context& c, const void* p, size_t bytes,
                                const char* what) {
   hipPointerAttribute_t attr{};
   const hipError_t e = hipPointerGetAttributes(&attr, p);
   if (e != hipSuccess) (void)hipGetLastError();
-  const bool dev = e == hipSuccess && (attr.type == hipMemoryTypeDevice ||
-                                       attr.type == hipMemoryTypeManaged);
-  CTM_REQUIRE(dev, std::string(what) + " is not device memory");
-  CTM_REQUIRE(attr.type == hipMemoryTypeManaged || attr.device == c.device,
+  CTM_REQUIRE(e == hipSuccess && attr.type == hipMemoryTypeDevice,
+              std::string(what) + " is not device memory");
+  CTM_REQUIRE(attr.device == c.device,
               std::string(what) + " lives on another device than the context's");
   hipDeviceptr_t base = nullptr;
   size_t size = 0;
