@@ -58,28 +58,32 @@ constexpr int kChunk = 128;  // K chunk of exact FP32 accumulation (BF16 path)
 // ------------------------------------------------------------ slicing
 
 // max |x| over each row r of the R x K view (element (r, k) at p[r rs + k]),
-// one workgroup per row.
+// one workgroup per row; rows are 16-byte aligned (the dispatcher checks p
+// and an even rs).  It also clears zero_out[0..nzero) for the column maxima
+// that follow on the same stream.
 __global__ __launch_bounds__(256) void rowmax_contig_kernel(const double* __restrict__ p,
                                                             long long rs, int K,
-                                                            double* __restrict__ mx) {
-  __shared__ double sh[256];
-  const int r = blockIdx.x;
+                                                            double* __restrict__ mx,
+                                                            double* __restrict__ zero_out,
+                                                            int nzero) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x, t = threadIdx.x;
+  for (int i = blockIdx.x * 256 + t; i < nzero; i += gridDim.x * 256) zero_out[i] = 0.0;
+  auto take = [](double m, double v) { return (v > m || v != v) ? v : m; };  // a NaN wins
   const double* row = p + r * rs;
-  double m = 0.0;
-  for (int k = threadIdx.x; k < K; k += 256) {
-    const double v = fabs(row[k]);
-    m = (v > m || v != v) ? v : m;  // a NaN wins
+  double m0 = 0.0, m1 = 0.0;
+  for (int k = 2 * t; k + 1 < K; k += 512) {
+    const d2v v = *(const d2v*)(row + k);
+    m0 = take(m0, fabs(v.x));
+    m1 = take(m1, fabs(v.y));
   }
-  sh[threadIdx.x] = m;
+  if ((K & 1) && t == 0) m0 = take(m0, fabs(row[K - 1]));
+  double m = take(m0, m1);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = take(m, __shfl_xor(m, off, 64));
+  if ((t & 63) == 0) sh[t >> 6] = m;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const double o = sh[threadIdx.x + s];
-      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) mx[r] = sh[0];
+  if (t == 0) mx[r] = take(take(sh[0], sh[1]), take(sh[2], sh[3]));
 }
 
 // max |x| over each column n of a K x N row-major matrix (row stride ld):
@@ -92,11 +96,20 @@ __global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ 
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= N) return;
   const int k0 = blockIdx.y * kslab, k1 = min(K, k0 + kslab);
-  double m = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    const double v = fabs(p[k * ld + n]);
-    m = (v > m || v != v) ? v : m;
+  auto take = [](double m, double v) { return (v > m || v != v) ? v : m; };  // a NaN wins
+  // four independent loads in flight per step
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  int k = k0;
+  for (; k + 3 < k1; k += 4) {
+    const double v0 = fabs(p[(long long)k * ld + n]), v1 = fabs(p[(long long)(k + 1) * ld + n]);
+    const double v2 = fabs(p[(long long)(k + 2) * ld + n]), v3 = fabs(p[(long long)(k + 3) * ld + n]);
+    m0 = take(m0, v0);
+    m1 = take(m1, v1);
+    m2 = take(m2, v2);
+    m3 = take(m3, v3);
   }
+  for (; k < k1; ++k) m0 = take(m0, fabs(p[(long long)k * ld + n]));
+  const double m = take(take(m0, m1), take(m2, m3));
   atomicMax(mx + n, (unsigned long long)__double_as_longlong(m));
 }
 
@@ -476,10 +489,11 @@ void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda
   __bf16* Bq = Aq + aq;
   double* amax = (double*)(((uintptr_t)(Bq + bq) + 255) & ~(uintptr_t)255);
   double* bmax = amax + M;
-  // maxima: rows of A (contiguous), columns of B (atomic max over K slabs)
-  hipLaunchKernelGGL(rowmax_contig_kernel, dim3(M), dim3(256), 0, ctx.stream, A, lda, K, amax);
-  fill_zero(ctx, bmax, (size_t)N);
-  const int kslab = 64;
+  // maxima: rows of A (contiguous; that kernel also clears bmax), columns of
+  // B (atomic max over K slabs)
+  hipLaunchKernelGGL(rowmax_contig_kernel, dim3(M), dim3(256), 0, ctx.stream, A, lda, K, amax,
+                     bmax, N);
+  const int kslab = 32;
   hipLaunchKernelGGL(colmax_kernel, dim3((N + 255) / 256, (K + kslab - 1) / kslab), dim3(256), 0,
                      ctx.stream, B, ldb, K, N, kslab, (unsigned long long*)bmax);
   CTM_HIP(hipGetLastError());
