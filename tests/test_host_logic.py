@@ -1,0 +1,94 @@
+"""Host-side logic of the benchmark and of the profile summaries (no GPU).
+
+* the algorithmic work per absorption move that the benchmark's headline
+  divides by: W = 5 chi^2 d^4 + 3 chi^3 d^3 + 8 chi^3 d^2 + 6 chi^3 d
+  multiply-adds, 1.995e11 flop at D = 6, chi = 72 (d = 36);
+* the traffic reader, which must hand out the stored HBM bytes only while the
+  kernel source still hashes to the value recorded with them;
+* the counter scaling of the traffic summary on a synthetic counter file;
+* the refusal of a multi-GPU run.
+"""
+import csv
+import io
+import os
+import subprocess
+import sys
+from contextlib import redirect_stdout
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1906_02220_amd import profsummary  # noqa: E402
+
+
+def test_algorithmic_work_per_move():
+    chi, d = 72, 36
+    w = 5 * chi**2 * d**4 + 3 * chi**3 * d**3 + 8 * chi**3 * d**2 + 6 * chi**3 * d
+    assert bench.move_macs(chi, d) == pytest.approx(w, rel=0, abs=0.5)
+    assert 2.0 * bench.move_macs(chi, d) == pytest.approx(1.995e11, rel=1e-3)
+
+
+def test_traffic_is_reported_only_for_the_recorded_kernel_source(tmp_path, monkeypatch):
+    src_dir = tmp_path / "paper_1906_02220_amd" / "csrc"
+    src_dir.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (src_dir / "gemm_f64.hip").write_text("kernel source, version 1\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h = bench.kernel_source_hash("gemm_f64.hip")
+    (tmp_path / "profiles" / "traffic_dgemm_rr_cut_D6_chi72.txt").write_text(
+        "# comment: with a colon\nkernel: dgemm_rr\nhbm_bytes_per_launch: 474028539\n"
+        "gemm_source_sha256_16: %s\n" % h)
+    assert bench.read_traffic(0) == 474028539
+    assert bench.read_traffic(1) is None  # no summary for the FP32 mode
+    (src_dir / "gemm_f64.hip").write_text("kernel source, version 2\n")
+    assert bench.read_traffic(0) is None
+
+
+def _counter_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_summary_scales_counters_by_the_copy(tmp_path):
+    copy_bytes = 1 << 20
+    # the copy kernel's counter reads half the true bytes for FETCH, all of
+    # them for WRITE; a smaller copy grid must be ignored
+    _counter_csv(tmp_path / "cf.csv", [
+        {"Kernel_Name": "copyBuffer", "Grid_Size": 4096, "Counter_Value": 512.0},
+        {"Kernel_Name": "copyBuffer", "Grid_Size": 64, "Counter_Value": 1.0}])
+    _counter_csv(tmp_path / "cw.csv", [
+        {"Kernel_Name": "copyBuffer", "Grid_Size": 4096, "Counter_Value": 1024.0}])
+    _counter_csv(tmp_path / "f.csv", [
+        {"Kernel_Name": "gemm_x<3>", "Grid_Size": 1, "Counter_Value": v} for v in (100.0, 300.0, 200.0)]
+        + [{"Kernel_Name": "other", "Grid_Size": 1, "Counter_Value": 9e9}])
+    _counter_csv(tmp_path / "w.csv", [
+        {"Kernel_Name": "gemm_x<3>", "Grid_Size": 1, "Counter_Value": 50.0}])
+    src = tmp_path / "k.hip"
+    src.write_text("x")
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        profsummary.main(["traffic", "--kernel", "gemm_x", "--fetch", str(tmp_path / "f.csv"),
+                          "--write", str(tmp_path / "w.csv"), "--copy-fetch", str(tmp_path / "cf.csv"),
+                          "--copy-write", str(tmp_path / "cw.csv"), "--copy-bytes", str(copy_bytes),
+                          "--source", str(src)])
+    kv = dict(line.split(": ", 1) for line in buf.getvalue().splitlines())
+    assert float(kv["fetch_scale"]) == pytest.approx(2.0)
+    assert float(kv["write_scale"]) == pytest.approx(1.0)
+    assert kv["dispatches"] == "3 fetch, 1 write"
+    assert float(kv["hbm_fetch_bytes_per_launch"]) == pytest.approx(200.0 * 1024 * 2.0)
+    assert float(kv["hbm_bytes_per_launch"]) == pytest.approx(200.0 * 1024 * 2.0 + 50.0 * 1024)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout == ""
