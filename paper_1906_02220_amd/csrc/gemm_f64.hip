@@ -374,8 +374,17 @@ __global__ void splitk_reduce_kernel(int M, int N, int ksplit, int batch, double
     const long long rem = idx - bt * MN;
     const int m = (int)(rem / N), n = (int)(rem - (long long)(rem / N) * N);
     const double* w = W + bt * ksplit * MN + rem;
+    // eight loads in flight, then the sums in split order
     double s = 0.0;
-    for (int z = 0; z < ksplit; ++z) s += w[z * MN];
+    int z = 0;
+    for (; z + 8 <= ksplit; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = w[(z + u) * MN];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < ksplit; ++z) s += w[z * MN];
     double* c = C + bt * cbs + (long long)m * crs + (long long)n * ccs;
     const double v = alpha * s;
     *c = (beta == 0.0) ? v : v + beta * (*c);
@@ -594,7 +603,15 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
   if (M >= 1024 && N >= 1024) { BM = 128; BN = 128; }
   else if (N <= 48) { BM = 64; BN = 32; }
   else { BM = 64; BN = 64; }
+  // The split-K factor follows from the tile count of this choice.  A skinny
+  // side of at most 96 then takes a narrower tile (64 x 32, or 32 x 64 when
+  // only M is small): less of the tile is padding, and since the K chunks do
+  // not change, neither does C.
   const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+  if (BM == 64 && BN == 64) {
+    if (N <= 96) BN = 32;
+    else if (M <= 96) BM = 32;
+  }
   const int BK = 16;
   int ksplit = 1;
   const long long target = 2LL * ctx.num_cus;
@@ -619,6 +636,7 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
   CTM_REQUIRE(grid.y <= 65535 && grid.z <= 65535, "gemm: grid too large");
   if (BM == 128) launch_cfg<128, 128, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
   else if (BN == 32) launch_cfg<64, 32, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
+  else if (BM == 32) launch_cfg<32, 64, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
   else launch_cfg<64, 64, 16, 2, 2>(ctx, akc, bnc, grid, M, N, K, alpha, A, B, beta, C, ksplit, kchunk, W);
   if (ksplit > 1) {
     const long long total = (long long)M * N * batch;
