@@ -27,9 +27,12 @@
 // exactly (ldexp).
 //
 // The slices are built by two memory-bound kernels (a max-abs reduction and
-// the split itself), stored K-contiguous for both operands so that a lane
-// reads the 8 consecutive k values an MFMA operand needs as one 16-byte LDS
-// read.
+// the split itself).  Both operands are stored K-step-major,
+// Q[k / 32][r][i][k % 32]: the S slices of a row's 32-wide K step are
+// contiguous, and so are all rows of one step.  The GEMM's K step then reads
+// whole 128-byte lines (a row-major slice would use half of each line per
+// step and fetch the other half again on the next), and a lane's MFMA
+// operand (8 consecutive k) is one 16-byte LDS read.
 //
 // MFMA operand fragments (checked on the device with an in-bounds probe):
 //   16x16x32 BF16: lane l holds A[l % 16][8 (l / 16) + e] and
@@ -140,8 +143,8 @@ __device__ inline void cut(double x, int e, __bf16* out) {
   }
 }
 
-// Slices of the R x K view (element (r, k) at p[r rs + k cs]) into
-// Q[i][r][k], row pitch Kp (zero for K <= k < Kp).  A 64 x 64 tile per
+// Slices of the R x K view (element (r, k) at p[r rs + k cs]) into the
+// K-step-major Q[k / 32][r][i][k % 32] (zero for K <= k < Kp).  A 64 x 64 tile per
 // workgroup goes through LDS so that the global reads are coalesced along
 // whichever index is contiguous and the slice writes along k.
 template <int S>
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
   const int r = r0 + rr;
   if (r >= R) return;
   const int e = scale_exponent(mx[r]);
-  const long long slab = (long long)R * Kp;
+  const long long step = (long long)R * S * 32;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int kb = k0 + kq + 8 * g;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
       bf8 w;
 #pragma unroll
       for (int u = 0; u < 8; ++u) w[u] = v[i][u];
-      *(bf8*)(Q + i * slab + (long long)r * Kp + kb) = w;
+      *(bf8*)(Q + (kb >> 5) * step + (long long)r * (S * 32) + i * 32 + (kb & 31)) = w;
     }
   }
 }
@@ -209,8 +212,9 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
 // stores 2-way conflicted (half of all LDS cycles in the counters).
 __device__ inline int slice_pos(int r, int c) { return r * 32 + ((c ^ (((r >> 1) ^ (r >> 2)) & 3)) << 3); }
 
-// C (M x N, row stride ldc, FP64) = A B from the slices Aq[S][M][Kp] and
-// Bq[S][N][Kp] (B stored transposed) and the row / column maxima.  128 x 128
+// C (M x N, row stride ldc, FP64) = A B from the K-step-major slices of A
+// (Aq[Kp / 32][M][S][32]) and of B^T (Bq[Kp / 32][N][S][32]) and the row /
+// column maxima.  128 x 128
 // tile, 8 waves as 4 x 2, each wave 32 x 64 (2 x 4 MFMA tiles); K steps of
 // 32 through double-buffered LDS with a register prefetch of the next step.
 template <int S, int TAG, int XG = 8>
@@ -227,19 +231,21 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
   int tm, tn;
   xcd_tile<XG>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
-  const long long aslab = (long long)M * Kp, bslab = (long long)N * Kp;
-  // global -> register mapping: thread t loads 16 bytes (8 k) of row t / 4
+  const long long astep = (long long)M * S * BK, bstep = (long long)N * S * BK;
+  // global -> register mapping: thread t loads 16 bytes (8 k) of every slice
+  // of row t / 4
   const int lrow = tid >> 2, lk = (tid & 3) * 8;
   const bool arow_ok = (m0 + lrow) < M, brow_ok = (n0 + lrow) < N;
-  const __bf16* ag = Aq + (long long)(m0 + lrow) * Kp + lk;
-  const __bf16* bg = Bq + (long long)(n0 + lrow) * Kp + lk;
+  const __bf16* ag = Aq + (long long)(m0 + lrow) * (S * BK) + lk;
+  const __bf16* bg = Bq + (long long)(n0 + lrow) * (S * BK) + lk;
   const int spos = slice_pos(lrow, tid & 3);
   u4 ra[S], rb[S];
   auto load = [&](int kt) {
+    const long long st = kt / BK;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      ra[i] = arow_ok ? *(const u4*)(ag + i * aslab + kt) : u4{0, 0, 0, 0};
-      rb[i] = brow_ok ? *(const u4*)(bg + i * bslab + kt) : u4{0, 0, 0, 0};
+      ra[i] = arow_ok ? *(const u4*)(ag + st * astep + i * BK) : u4{0, 0, 0, 0};
+      rb[i] = brow_ok ? *(const u4*)(bg + st * bstep + i * BK) : u4{0, 0, 0, 0};
     }
   };
   auto store = [&](int buf) {
@@ -497,7 +503,7 @@ void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda
   hipLaunchKernelGGL(colmax_kernel, dim3((N + 255) / 256, (K + kslab - 1) / kslab), dim3(256), 0,
                      ctx.stream, B, ldb, K, N, kslab, (unsigned long long*)bmax);
   CTM_HIP(hipGetLastError());
-  // slices: A as [M][Kp] (rows contiguous), B^T as [N][Kp] (columns of B)
+  // slices, K-step-major: A by rows, B^T (the columns of B)
   hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (M + 63) / 64),
                      dim3(256), 0, ctx.stream, A, lda, 1LL, M, K, Kp, amax, Aq);
   hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (N + 63) / 64),
