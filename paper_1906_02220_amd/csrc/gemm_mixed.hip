@@ -203,6 +203,17 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
 
 // ------------------------------------------------------------ BF16 slice GEMM
 
+// 16 bytes per lane from global memory straight into LDS, lane l's bytes at
+// LDS address lds + 16 l (lds wave-uniform, through M0).  Written as inline
+// asm so that the compiler, which cannot tell these LDS writes from the
+// fragment reads of the other stage, does not wait for them before every LDS
+// read; the kernel waits for them itself (vmcnt) before its barriers.  The
+// instruction has no register result.
+__device__ inline void load_to_lds16(const void* g, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds)
+               : "memory", "m0");
+}
+
 // LDS position (in BF16 units) of the 16-byte chunk c (8 consecutive k) of
 // row r in a 32-wide K step: rows are 64 bytes, unpadded, and the chunk index
 // is XORed with ((r >> 1) ^ (r >> 2)) & 3.  Both the operand reads (16
@@ -216,7 +227,12 @@ __device__ inline int slice_pos(int r, int c) { return r * 32 + ((c ^ (((r >> 1)
 // (Aq[Kp / 32][M][S][32]) and of B^T (Bq[Kp / 32][N][S][32]) and the row /
 // column maxima.  128 x 128
 // tile, 8 waves as 4 x 2, each wave 32 x 64 (2 x 4 MFMA tiles); K steps of
-// 32 through double-buffered LDS with a register prefetch of the next step.
+// 32 through two LDS stages, the next step loaded straight into the other
+// stage while this one is multiplied.  Wave w moves rows 16 w .. 16 w + 15 of
+// every slice of both operands (1 KB per slice and operand): lane l fetches
+// the chunk whose swizzled LDS slot is byte 16 l of the wave's kilobyte.
+// Rows past M (N) repeat row M - 1 (N - 1); they only reach accumulator rows
+// (columns) that are not stored.
 template <int S, int TAG, int XG = 8>
 __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     int M, int N, int Kp, const __bf16* __restrict__ Aq, const __bf16* __restrict__ Bq,
@@ -224,36 +240,38 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     int ldc) {
   constexpr int BM = 128, BN = 128, BK = 32;
   constexpr int TI = 2, TJ = 4;
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][S][BM * BK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][S][BN * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 As[2][S][BM * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 Bs[2][S][BN * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
   int tm, tn;
   xcd_tile<XG>(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const long long astep = (long long)M * S * BK, bstep = (long long)N * S * BK;
-  // global -> register mapping: thread t loads 16 bytes (8 k) of every slice
-  // of row t / 4
-  const int lrow = tid >> 2, lk = (tid & 3) * 8;
-  const bool arow_ok = (m0 + lrow) < M, brow_ok = (n0 + lrow) < N;
-  const __bf16* ag = Aq + (long long)(m0 + lrow) * (S * BK) + lk;
-  const __bf16* bg = Bq + (long long)(n0 + lrow) * (S * BK) + lk;
-  const int spos = slice_pos(lrow, tid & 3);
-  u4 ra[S], rb[S];
-  auto load = [&](int kt) {
+  const int lr = 16 * wave + (lane >> 2);                     // tile row this lane moves
+  const int lc = (lane & 3) ^ (((lr >> 1) ^ (lr >> 2)) & 3);  // its chunk at LDS slot lane & 3
+  const __bf16* ag = Aq + (long long)min(m0 + lr, M - 1) * (S * BK) + 8 * lc;
+  const __bf16* bg = Bq + (long long)min(n0 + lr, N - 1) * (S * BK) + 8 * lc;
+  const unsigned a_lds = __builtin_amdgcn_readfirstlane(
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) __bf16*)&As[0][0][16 * wave * BK]);
+  const unsigned b_lds = __builtin_amdgcn_readfirstlane(
+      (unsigned)(uintptr_t)(__attribute__((address_space(3))) __bf16*)&Bs[0][0][16 * wave * BK]);
+  constexpr unsigned slice_bytes = BM * BK * 2, stage_bytes = S * slice_bytes;
+  static_assert(BM == BN, "A and B stages share the byte strides");
+  auto load = [&](int kt, int buf) {
     const long long st = kt / BK;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      ra[i] = arow_ok ? *(const u4*)(ag + st * astep + i * BK) : u4{0, 0, 0, 0};
-      rb[i] = brow_ok ? *(const u4*)(bg + st * bstep + i * BK) : u4{0, 0, 0, 0};
+      load_to_lds16(ag + st * astep + i * BK, a_lds + buf * stage_bytes + i * slice_bytes);
+      load_to_lds16(bg + st * bstep + i * BK, b_lds + buf * stage_bytes + i * slice_bytes);
     }
   };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      *(u4*)(&As[buf][i][spos]) = ra[i];
-      *(u4*)(&Bs[buf][i][spos]) = rb[i];
-    }
+  // every load of this wave has landed, every LDS read has returned, then all
+  // waves meet
+  auto step_barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    asm volatile("s_barrier" ::: "memory");
   };
   f4 acc0[TI][TJ], accr[TI][TJ];
   double acc[TI][TJ][4];
@@ -279,13 +297,13 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
         accr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       }
   };
-  load(0);
-  store(0);
-  __syncthreads();
+  load(0, 0);
+  step_barrier();
   int buf = 0;
   for (int kt = 0; kt < Kp; kt += BK) {
     const bool more = kt + BK < Kp;
-    if (more) load(kt + BK);
+    // the other stage was last read in the previous step, behind the barrier
+    if (more) load(kt + BK, buf ^ 1);
     bf8 a[TI][S];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -309,8 +327,7 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
       }
     }
     if (((kt + BK) % kChunk) == 0 || !more) flush();
-    if (more) store(buf ^ 1);
-    __syncthreads();
+    step_barrier();
     buf ^= 1;
   }
   // epilogue: C = acc 2^(eA + eB - 16)
