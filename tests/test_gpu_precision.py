@@ -87,6 +87,23 @@ def test_mixed_modes_ragged_shapes(ctx, mode):
     assert de < GATE_H[mode]
 
 
+@pytest.mark.parametrize("mode", [ctm.CTM_PREC_BF16X3, ctm.CTM_PREC_BF16X4])
+@pytest.mark.parametrize("chi", [1, 2, 3])
+def test_slice_modes_tiny_products(ctx, mode, chi):
+    """D = 2 (d = 4), chi = 1..3: the slice products have M, N below 16
+    (every wave of the 128 x 128 tile repeats the last valid row) and K at
+    most one 32-wide step, which the slice GEMM must handle like any other
+    shape."""
+    A, B, H, k_o, e_o, _ = _oracle(2, chi, 6, 21)
+    say("case: D=2 chi=%d precision mode %d" % (chi, mode))
+    env = ctm.Environment.from_purification(ctx, A, B, 2, chi, precision=mode)
+    env.sweep(6, 0.0)
+    dk, de = abs(env.norm() / k_o - 1.0), abs(env.expect(H) - e_o)
+    say("  kappa rel %.3e  <H> abs %.3e" % (dk, de))
+    assert dk < GATE[mode]
+    assert de < GATE_H[mode]
+
+
 def _golden(sweeps):
     with open(os.path.join(HERE, "golden", "c3_D6_chi72_%d_sweeps.json" % sweeps)) as f:
         return json.load(f)
