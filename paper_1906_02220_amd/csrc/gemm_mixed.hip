@@ -155,19 +155,43 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
   __shared__ double tile[64][65];
   const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
   const int t = threadIdx.x;
+  // 16-byte loads of two neighbours along the contiguous index (the caller
+  // passes a 16-byte aligned p and an even stride)
   if (cs == 1) {
     // rows contiguous along k: consecutive threads walk k
-    for (int idx = t; idx < 64 * 64; idx += 256) {
-      const int rr = idx >> 6, kk = idx & 63;
+    for (int idx = t; idx < 64 * 32; idx += 256) {
+      const int rr = idx >> 5, kk = (idx & 31) * 2;
       const int r = r0 + rr, k = k0 + kk;
-      tile[rr][kk] = (r < R && k < K) ? p[r * rs + k] : 0.0;
+      double v0 = 0.0, v1 = 0.0;
+      if (r < R) {
+        if (k + 1 < K) {
+          const d2v v = *(const d2v*)(p + r * rs + k);
+          v0 = v.x;
+          v1 = v.y;
+        } else if (k < K) {
+          v0 = p[r * rs + k];
+        }
+      }
+      tile[rr][kk] = v0;
+      tile[rr][kk + 1] = v1;
     }
   } else {
-    // contiguous along r: consecutive threads walk r
-    for (int idx = t; idx < 64 * 64; idx += 256) {
-      const int kk = idx >> 6, rr = idx & 63;
+    // contiguous along r (rs == 1): consecutive threads walk r
+    for (int idx = t; idx < 64 * 32; idx += 256) {
+      const int kk = idx >> 5, rr = (idx & 31) * 2;
       const int r = r0 + rr, k = k0 + kk;
-      tile[rr][kk] = (r < R && k < K) ? p[r * rs + k * cs] : 0.0;
+      double v0 = 0.0, v1 = 0.0;
+      if (k < K) {
+        if (r + 1 < R) {
+          const d2v v = *(const d2v*)(p + r + k * cs);
+          v0 = v.x;
+          v1 = v.y;
+        } else if (r < R) {
+          v0 = p[r + k * cs];
+        }
+      }
+      tile[rr][kk] = v0;
+      tile[rr + 1][kk] = v1;
     }
   }
   __syncthreads();
