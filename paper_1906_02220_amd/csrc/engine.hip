@@ -215,12 +215,17 @@ void Env::corner(int f) {
   const long long d4[4] = {chi, d, d, chi};
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t1.d(), t2.d(), 4, d4, p0321);  // [de,ga,u,l]
-  // t1 = t2 a_f : [(de,ga),(u,l)] x [(u,l),(dd,r)]
-  gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
-             rowmajor(arot[f].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));
-  const long long e4[4] = {chi, chi, d, d};
-  const int p0213[4] = {0, 2, 1, 3};
-  permute(ctx, t1.d(), Qb[f].d(), 4, e4, p0213);  // [de,dd,ga,r]
+  // Q_f = (t2 a_f) [(de,ga),(u,l)] x [(u,l),(dd,r)], stored [de,dd,ga,r]: the
+  // slice modes write that order from the product itself
+  const OutMap to_q{chi, (long long)d * chi * d, d, d, (long long)chi * d};
+  if (!gemm_slices_split_out(ctx, opt.precision, chi * chi, d * d, d * d, rowmajor(t2.d(), d * d),
+                             rowmajor(arot[f].d(), d * d), Qb[f].d(), to_q)) {
+    gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
+               rowmajor(arot[f].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));
+    const long long e4[4] = {chi, chi, d, d};
+    const int p0213[4] = {0, 2, 1, 3};
+    permute(ctx, t1.d(), Qb[f].d(), 4, e4, p0213);  // [de,dd,ga,r]
+  }
   qvalid[f] = true;
 }
 
@@ -377,12 +382,20 @@ void Env::move_back(int k) {
   const long long d4[4] = {chi, d, d, chi};
   const int p0321[4] = {0, 3, 2, 1};
   permute(ctx, t1.d(), t2.d(), 4, d4, p0321);  // [de,k2,u,l]
-  gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
-             rowmajor(arot[q0].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));  // [de,k2,dd,r]
-  const long long e4[4] = {chi, chi, d, d};
-  const int p0213[4] = {0, 2, 1, 3};
-  permute(ctx, t1.d(), t2.d(), 4, e4, p0213);  // [de,dd,k2,r]
-  gemm_f64(ctx, chi, dc, n, 1.0, colmajor(Pu.d(), chi), rowmajor(t2.d(), dc), 0.0,
+  // (t2 a) [de,k2,dd,r], stored [de,dd,k2,r] (by the product itself in the slice modes)
+  const OutMap to_t{chi, (long long)d * chi * d, d, d, (long long)chi * d};
+  const double* tq = t2.d();  // [de,dd,k2,r]
+  if (gemm_slices_split_out(ctx, opt.precision, chi * chi, d * d, d * d, rowmajor(t2.d(), d * d),
+                            rowmajor(arot[q0].d(), d * d), t1.d(), to_t)) {
+    tq = t1.d();
+  } else {
+    gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
+               rowmajor(arot[q0].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));  // [de,k2,dd,r]
+    const long long e4[4] = {chi, chi, d, d};
+    const int p0213[4] = {0, 2, 1, 3};
+    permute(ctx, t1.d(), t2.d(), 4, e4, p0213);  // [de,dd,k2,r]
+  }
+  gemm_f64(ctx, chi, dc, n, 1.0, colmajor(Pu.d(), chi), rowmajor(tq, dc), 0.0,
            out_rowmajor(sm2.d(), dc));  // [k1][k2,r]
   const long long e3[3] = {chi, chi, d};
   const int p021[3] = {0, 2, 1};

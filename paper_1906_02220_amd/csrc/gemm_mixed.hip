@@ -261,7 +261,7 @@ template <int S, int TAG, int XG = 8>
 __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     int M, int N, int Kp, const __bf16* __restrict__ Aq, const __bf16* __restrict__ Bq,
     const double* __restrict__ amax, const double* __restrict__ bmax, double* __restrict__ C,
-    int ldc) {
+    OutMap om) {
   constexpr int BM = 128, BN = 128, BK = 32;
   constexpr int TI = 2, TJ = 4;
   __shared__ __attribute__((aligned(1024))) __bf16 As[2][S][BM * BK];
@@ -354,8 +354,20 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     step_barrier();
     buf ^= 1;
   }
-  // epilogue: C = acc 2^(eA + eB - 16)
+  // epilogue: C = acc 2^(eA + eB - 16), placed by om (the row and column
+  // parts of the offset are computed once per row and per column)
   const int lq = lane >> 4;
+  long long coff[TJ];
+  int eb[TJ];
+  bool bbad[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int gn = n0 + wn + 16 * j + fr;
+    const int g = gn < N ? gn : 0;
+    coff[j] = (long long)(g / om.c2) * om.sc1 + g % om.c2;
+    eb[j] = scale_exponent(bmax[g]);
+    bbad[j] = !(bmax[g] < INFINITY);
+  }
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -364,13 +376,13 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
       if (gm >= M) continue;
       const int ea = scale_exponent(amax[gm]);
       const bool abad = !(amax[gm] < INFINITY);
+      const long long roff = (long long)(gm / om.r2) * om.sr1 + (long long)(gm % om.r2) * om.sr2;
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
         const int gn = n0 + wn + 16 * j + fr;
         if (gn < N) {
-          const double bm = bmax[gn];
-          const double v = ldexp(acc[i][j][r], ea + scale_exponent(bm) - 16);
-          C[(long long)gm * ldc + gn] = (abad || !(bm < INFINITY)) ? NAN : v;
+          const double v = ldexp(acc[i][j][r], ea + eb[j] - 16);
+          C[roff + coff[j]] = (abad || bbad[j]) ? NAN : v;
         }
       }
     }
@@ -522,7 +534,7 @@ namespace {
 
 template <int S>
 void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda,
-               const double* B, long long ldb, double* C, long long ldc, int cls) {
+               const double* B, long long ldb, double* C, const OutMap& om, int cls) {
   const int tag = cls == 0 ? 0 : 1;
   const int Kp = (K + 31) / 32 * 32;
   const size_t aq = (size_t)S * M * Kp, bq = (size_t)S * N * Kp;
@@ -556,10 +568,10 @@ void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda
   ScopedTimer t0(ctx, cls == 0 ? 0 : -1, 2.0 * M * N * (double)K);
   if (tag == 0)
     hipLaunchKernelGGL((gemm_bf16s_kernel<S, 0>), dim3((unsigned)tiles), dim3(512), 0, ctx.stream,
-                       M, N, Kp, Aq, Bq, amax, bmax, C, (int)ldc);
+                       M, N, Kp, Aq, Bq, amax, bmax, C, om);
   else
     hipLaunchKernelGGL((gemm_bf16s_kernel<S, 1>), dim3((unsigned)tiles), dim3(512), 0, ctx.stream,
-                       M, N, Kp, Aq, Bq, amax, bmax, C, (int)ldc);
+                       M, N, Kp, Aq, Bq, amax, bmax, C, om);
   CTM_HIP(hipGetLastError());
 }
 
@@ -652,10 +664,22 @@ void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View 
     };
     run(pick_variant(ctx, 1, M, N, K, cls, 3, run));
   } else if (mode == CTM_PREC_BF16X3) {
-    run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, C.rs, cls);
+    run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, OutMap::plain(M, N, C.rs), cls);
   } else {
-    run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, C.rs, cls);
+    run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C.p, OutMap::plain(M, N, C.rs), cls);
   }
+}
+
+bool gemm_slices_split_out(Context& ctx, int mode, int M, int N, int K, View A, View B, double* C,
+                           const OutMap& om, int cls) {
+  if (mode != CTM_PREC_BF16X3 && mode != CTM_PREC_BF16X4) return false;
+  // the operand conditions of the slice path; C's placement is om's
+  if (!mixed_plain(mode, M, N, K, 1.0, A, B, 0.0, ViewOut{C, (long long)N, 1, 0}, 1)) return false;
+  CTM_REQUIRE(om.r2 >= 1 && om.c2 >= 1, "gemm_slices_split_out: bad output map");
+  ScopedTimer t1(ctx, 1, 2.0 * M * N * (double)K);
+  if (mode == CTM_PREC_BF16X3) run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls);
+  else run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls);
+  return true;
 }
 
 }  // namespace ctm

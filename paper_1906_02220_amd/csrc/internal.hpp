@@ -200,6 +200,26 @@ void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View 
 // Modes gemm_mixed implements.
 bool mixed_mode_supported(int mode);
 
+// Where a product writes element (i, j): C[(i / r2) sr1 + (i % r2) sr2 +
+// (j / c2) sc1 + j % c2], i.e. rows and columns each split into two indices,
+// so that a permutation that keeps the last column index innermost can be
+// written by the product itself.  plain(M, N, ldc) is the row-major layout.
+struct OutMap {
+  int r2;
+  long long sr1, sr2;
+  int c2;
+  long long sc1;
+  static OutMap plain(int M, int N, long long ldc) { return OutMap{M, 0, ldc, N, 0}; }
+  __host__ __device__ long long at(int i, int j) const {
+    return (long long)(i / r2) * sr1 + (long long)(i % r2) * sr2 + (long long)(j / c2) * sc1 + j % c2;
+  }
+};
+// C = A B through `om` when `mode` is a BF16 slice mode and the slice kernel
+// covers the product (returns true); otherwise nothing runs and it returns
+// false, and the caller takes the plain path.
+bool gemm_slices_split_out(Context& ctx, int mode, int M, int N, int K, View A, View B, double* C,
+                           const OutMap& om, int cls = -1);
+
 // out = permutation of `in` (row-major dims[0..rank-1]); out axis a is in
 // axis perm[a].  rank <= 8.
 void permute(Context& ctx, const double* in, double* out, int rank, const long long* dims,
