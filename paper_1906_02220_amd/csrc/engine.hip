@@ -128,6 +128,7 @@ void Env::set_site_tensor_dev(const double* a_dev) {
   const long long dims[4] = {d, d, d, d};
   const int rot[4] = {3, 0, 1, 2};
   for (int k = 1; k < 4; ++k) permute(ctx, arot[k - 1].d(), arot[k].d(), 4, dims, rot);
+  for (int k = 0; k < 4; ++k) aslices[k].valid = false;
   e_valid = false;
 }
 
@@ -219,7 +220,7 @@ void Env::corner(int f) {
   // slice modes write that order from the product itself
   const OutMap to_q{chi, (long long)d * chi * d, d, d, (long long)chi * d};
   if (!gemm_slices_split_out(ctx, opt.precision, chi * chi, d * d, d * d, rowmajor(t2.d(), d * d),
-                             rowmajor(arot[f].d(), d * d), Qb[f].d(), to_q)) {
+                             rowmajor(arot[f].d(), d * d), Qb[f].d(), to_q, -1, &aslices[f])) {
     gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),
                rowmajor(arot[f].d(), d * d), 0.0, out_rowmajor(t1.d(), d * d));
     const long long e4[4] = {chi, chi, d, d};
@@ -386,7 +387,7 @@ void Env::move_back(int k) {
   const OutMap to_t{chi, (long long)d * chi * d, d, d, (long long)chi * d};
   const double* tq = t2.d();  // [de,dd,k2,r]
   if (gemm_slices_split_out(ctx, opt.precision, chi * chi, d * d, d * d, rowmajor(t2.d(), d * d),
-                            rowmajor(arot[q0].d(), d * d), t1.d(), to_t)) {
+                            rowmajor(arot[q0].d(), d * d), t1.d(), to_t, -1, &aslices[q0])) {
     tq = t1.d();
   } else {
     gemm_mixed(ctx, opt.precision, chi * chi, d * d, d * d, 1.0, rowmajor(t2.d(), d * d),

@@ -119,6 +119,7 @@ class Env {
   double* Tw(int i) { return Tall.d() + (size_t)(i & 3) * chi * d * chi; }
 
   DevBuf arot[4];
+  SliceCache aslices[4];    // BF16 slices of arot[f], valid until the site tensor changes
   DevBuf Kc;                // composite 16 x D^4
   DevBuf Call, Tall;        // 4 chi^2, 4 chi^2 d
   DevBuf logs;              // 8 log scales

@@ -534,7 +534,8 @@ namespace {
 
 template <int S>
 void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda,
-               const double* B, long long ldb, double* C, const OutMap& om, int cls) {
+               const double* B, long long ldb, double* C, const OutMap& om, int cls,
+               SliceCache* bc = nullptr) {
   const int tag = cls == 0 ? 0 : 1;
   const int Kp = (K + 31) / 32 * 32;
   const size_t aq = (size_t)S * M * Kp, bq = (size_t)S * N * Kp;
@@ -548,19 +549,41 @@ void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda
   __bf16* Bq = Aq + aq;
   double* amax = (double*)(((uintptr_t)(Bq + bq) + 255) & ~(uintptr_t)255);
   double* bmax = amax + M;
-  // maxima: rows of A (contiguous; that kernel also clears bmax), columns of
-  // B (atomic max over K slabs)
+  // a cached B is sliced once, into the cache, and reused while valid
+  bool slice_b = true;
+  if (bc) {
+    if (bc->valid && bc->S == S && bc->N == N && bc->K == K && bc->src == B) {
+      slice_b = false;
+    } else {
+      if (bc->q.bytes < bq * sizeof(__bf16) || bc->mx.bytes < (size_t)N * sizeof(double)) {
+        CTM_HIP(hipStreamSynchronize(ctx.stream));
+        bc->q.alloc(bq * sizeof(__bf16));
+        bc->mx.alloc((size_t)N * sizeof(double));
+      }
+      bc->S = S;
+      bc->N = N;
+      bc->K = K;
+      bc->src = B;
+      bc->valid = true;
+    }
+    Bq = (__bf16*)bc->q.p;
+    bmax = (double*)bc->mx.p;
+  }
+  // maxima: rows of A (contiguous; that kernel also clears bmax when B is
+  // sliced here), columns of B (atomic max over K slabs)
   hipLaunchKernelGGL(rowmax_contig_kernel, dim3(M), dim3(256), 0, ctx.stream, A, lda, K, amax,
-                     bmax, N);
+                     bmax, slice_b ? N : 0);
   const int kslab = 32;
-  hipLaunchKernelGGL(colmax_kernel, dim3((N + 255) / 256, (K + kslab - 1) / kslab), dim3(256), 0,
-                     ctx.stream, B, ldb, K, N, kslab, (unsigned long long*)bmax);
+  if (slice_b)
+    hipLaunchKernelGGL(colmax_kernel, dim3((N + 255) / 256, (K + kslab - 1) / kslab), dim3(256), 0,
+                       ctx.stream, B, ldb, K, N, kslab, (unsigned long long*)bmax);
   CTM_HIP(hipGetLastError());
   // slices, K-step-major: A by rows, B^T (the columns of B)
   hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (M + 63) / 64),
                      dim3(256), 0, ctx.stream, A, lda, 1LL, M, K, Kp, amax, Aq);
-  hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (N + 63) / 64),
-                     dim3(256), 0, ctx.stream, B, 1LL, ldb, N, K, Kp, bmax, Bq);
+  if (slice_b)
+    hipLaunchKernelGGL((split_kernel<S>), dim3(Kp / 64 + (Kp % 64 ? 1 : 0), (N + 63) / 64),
+                       dim3(256), 0, ctx.stream, B, 1LL, ldb, N, K, Kp, bmax, Bq);
   CTM_HIP(hipGetLastError());
   const long long tiles = (long long)((M + 127) / 128) * ((N + 127) / 128);
   CTM_REQUIRE(tiles <= INT_MAX, "gemm_mixed: grid too large");
@@ -671,14 +694,14 @@ void gemm_mixed(Context& ctx, int mode, int M, int N, int K, double alpha, View 
 }
 
 bool gemm_slices_split_out(Context& ctx, int mode, int M, int N, int K, View A, View B, double* C,
-                           const OutMap& om, int cls) {
+                           const OutMap& om, int cls, SliceCache* bc) {
   if (mode != CTM_PREC_BF16X3 && mode != CTM_PREC_BF16X4) return false;
   // the operand conditions of the slice path; C's placement is om's
   if (!mixed_plain(mode, M, N, K, 1.0, A, B, 0.0, ViewOut{C, (long long)N, 1, 0}, 1)) return false;
   CTM_REQUIRE(om.r2 >= 1 && om.c2 >= 1, "gemm_slices_split_out: bad output map");
   ScopedTimer t1(ctx, 1, 2.0 * M * N * (double)K);
-  if (mode == CTM_PREC_BF16X3) run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls);
-  else run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls);
+  if (mode == CTM_PREC_BF16X3) run_bf16s<3>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls, bc);
+  else run_bf16s<4>(ctx, M, N, K, A.p, A.rs, B.p, B.rs, C, om, cls, bc);
   return true;
 }
 

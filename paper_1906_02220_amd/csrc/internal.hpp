@@ -214,11 +214,21 @@ struct OutMap {
     return (long long)(i / r2) * sr1 + (long long)(i % r2) * sr2 + (long long)(j / c2) * sc1 + j % c2;
   }
 };
+// The slices and column maxima of a B operand that stays constant over many
+// products (the rotated site tensor): filled by the first product that uses
+// it, reused while `valid` (the owner clears it when B changes).
+struct SliceCache {
+  DevBuf q, mx;
+  int S = 0, N = 0, K = 0;
+  const void* src = nullptr;
+  bool valid = false;
+};
 // C = A B through `om` when `mode` is a BF16 slice mode and the slice kernel
 // covers the product (returns true); otherwise nothing runs and it returns
-// false, and the caller takes the plain path.
+// false, and the caller takes the plain path.  With bc, B's slices come from
+// (or go to) that cache.
 bool gemm_slices_split_out(Context& ctx, int mode, int M, int N, int K, View A, View B, double* C,
-                           const OutMap& om, int cls = -1);
+                           const OutMap& om, int cls = -1, SliceCache* bc = nullptr);
 
 // out = permutation of `in` (row-major dims[0..rank-1]); out axis a is in
 // axis perm[a].  rank <= 8.
