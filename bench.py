@@ -59,10 +59,11 @@ def executed_move_macs(chi, d):
     return corners + halves + proj + renorm
 
 
-def cpu_baseline(D, chi, seed, moves=20):
+def cpu_baseline(D, chi, seed, moves=16):
     """The FP64 oracle on the host cores: `moves` absorption moves from the
-    boundary start at the benchmark shape (each with a full LAPACK SVD of the
-    n x n cut matrix)."""
+    boundary start at the benchmark shape, cycling L, R, U, D (each with a
+    full LAPACK SVD of the n x n cut matrix).  The rate divides the
+    algorithmic work of exactly the moves that ran by their time."""
     from oracle import ctmrg as O
     from paper_1906_02220_amd import synth
     try:
@@ -75,15 +76,23 @@ def cpu_baseline(D, chi, seed, moves=20):
     a = O.double_layer(K)
     arot = [O.rotate(a, k) for k in range(4)]
     env = O.init_env(D * D, chi, O.boundary_vector_double_layer(D))
+    order = cpu_baseline_order(moves)
     t0 = time.perf_counter()
-    for k in (0, 2, 1, 3)[:moves]:
+    for k in order:
         O.left_move(env, arot, k, chi)
     dt = time.perf_counter() - t0
-    gflops = moves * 2.0 * move_macs(chi, D * D) / dt / 1e9
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d absorption moves from the boundary start at D=%d chi=%d (full LAPACK SVD "
-                      "of the %dx%d cut matrix per move), %.1f s" % (moves, D, chi, chi * D * D,
-                                                                    chi * D * D, dt)}
+    gflops = len(order) * 2.0 * move_macs(chi, D * D) / dt / 1e9
+    return {"value": float("%.6g" % gflops), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d absorption moves (%d sweeps L, R, U, D) from the boundary start at D=%d "
+                      "chi=%d, each with a full LAPACK SVD of the %dx%d cut matrix, %.1f s" % (
+                          len(order), len(order) // 4, D, chi, chi * D * D, chi * D * D, dt),
+            "moves": len(order), "seconds": dt}
+
+
+def cpu_baseline_order(moves):
+    """Directions of the CPU sample's moves: the sweep order L, R, U, D
+    repeated until `moves` moves."""
+    return [(0, 2, 1, 3)[i % 4] for i in range(moves)]
 
 
 COPY_BYTES = 512 << 20
@@ -154,21 +163,24 @@ KERNEL_NAMES = {0: "dgemm_rr<96,96,16,2,2,0,true,true>", 1: "gemm_f32x1_kernel<0
                 3: "gemm_bf16s_kernel<3,0,8>", 4: "gemm_bf16s_kernel<4,0,8>"}
 
 
-def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
-    """Converge, warm up and time `args.steps` sweeps in one precision mode;
-    then the bond metric, norm and <H_bond> of the converged environment."""
+def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args, converge=None):
+    """Converge, warm up and time `args.steps` sweeps in one precision mode
+    with per-launch timing off (the value); then as many sweeps again with
+    HIP events around every launch (the kernel averages of the roofline);
+    then the bond metric, norm and <H_bond> of the environment."""
     d = D * D
     n = chi * d
+    converge = args.converge if converge is None else converge
     env = ctm.Environment.from_purification(ctx, A, B, 2, chi, precision=mode)
     log("bench: mode %s: converging %d sweeps at D=%d chi=%d (n=%d)" % (
-        MODE_NAMES[mode], args.converge, D, chi, n))
+        MODE_NAMES[mode], converge, D, chi, n))
     t0 = time.perf_counter()
-    env.sweep(args.converge, 0.0)
-    log("bench: converged in %.2f s, kappa %.15g" % (time.perf_counter() - t0, env.norm()))
+    _, _, delta = env.sweep(converge, 0.0)
+    log("bench: converged in %.2f s, kappa %.15g, delta %.3e" % (time.perf_counter() - t0,
+                                                                 env.norm(), delta))
     for _ in range(args.warmup):
         env.sweep(1, 0.0)
-    ctx.timing(True)
-    ctx.timing_reset()
+    ctx.timing(False)
     torch.cuda.synchronize()
     per_sweep = []
     t0 = time.perf_counter()
@@ -178,24 +190,37 @@ def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
         per_sweep.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    kappa_prev, e_prev = env.norm(), env.expect(H)
+    # second pass: the same number of sweeps with per-launch HIP events
+    ctx.timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    _, _, delta = env.sweep(args.steps, 0.0)
+    torch.cuda.synchronize()
     c0, ms0, _ = ctx.timing_get(0)   # the n x n x n cut-matrix products
     c1, ms1, _ = ctx.timing_get(1)   # every dense contraction kernel
     c2, ms2, _ = ctx.timing_get(2)   # whole moves
     ctx.timing(False)
     moves = 4 * args.steps
     gflops = 2.0 * move_macs(chi, d) * moves / dt / 1e9
-    # roofline of the dominant kernel: one n x n x n product per launch;
-    # executed MFMA flops = slice products x 2 n^3, against the dtype's peak
-    per_launch = SLICE_PRODUCTS[mode] * 2.0 * float(n) ** 3
+    # roofline of the dominant kernel: one n x n x n product per launch, the
+    # method's 2 n^3 flops per launch against the peak of the dtype the
+    # kernel computes in; the executed MFMA flops (slice products x 2 n^3)
+    # are reported beside it
+    per_launch = 2.0 * float(n) ** 3
     avg_ms = ms0 / max(c0, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
+    executed = SLICE_PRODUCTS[mode] * achieved
     traffic = read_traffic(mode)
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[mode],
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[mode], 4),
             "traffic": traffic,
             "traffic_GBps": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
             "kernel": "%s (n x n x n, n=%d)" % (KERNEL_NAMES[mode], n),
-            "flops_per_launch": per_launch, "launches": c0, "avg_launch_ms": round(avg_ms, 4)}
+            "flops_per_launch": per_launch, "launches": c0, "avg_launch_ms": round(avg_ms, 4),
+            "slice_products_per_launch": SLICE_PRODUCTS[mode],
+            "executed_achieved": round(executed, 3),
+            "executed_frac": round(executed / PEAK_TFLOPS[mode], 4)}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kappa = env.norm()
@@ -203,12 +228,19 @@ def run_mode(ctx, ctm, torch, A, B, H, D, chi, mode, args):
     env.bond_metric()
     torch.cuda.synchronize()
     fu_ms = 1e3 * (time.perf_counter() - t1)
+    env.close()
     return {"gflops": gflops, "ms_per_move": 1e3 * dt / moves,
             "ms_per_move_median": 1e3 * float(np.median(per_sweep)) / 4.0,
+            "executed_gflops": 2.0 * executed_move_macs(chi, d) * moves / dt / 1e9,
             "pct_mfma_peak_of_dtype": 100.0 * gflops / (PEAK_TFLOPS[mode] * 1e3),
             "contraction_share_of_move_time": ms1 / max(ms2, 1e-9),
             "contraction_only_gflops": 2.0 * move_macs(chi, d) * moves / max(ms1 * 1e-3, 1e-12) / 1e9,
-            "roofline": roof, "fu_ms": fu_ms, "kappa": kappa, "energy_bond": e_h}
+            "roofline": roof, "fu_ms": fu_ms, "kappa": kappa, "energy_bond": e_h,
+            "delta_last_sweep": delta,
+            # how far the environment itself still moves over the last
+            # args.steps sweeps: the floor under any comparison of modes
+            "self_change_kappa": abs(kappa / kappa_prev - 1.0),
+            "self_change_energy": abs(e_h - e_prev)}
 
 
 def run_structured(ctx, ctm, torch, synth, H, D, chi, modes, args):
@@ -217,24 +249,33 @@ def run_structured(ctx, ctm, torch, synth, H, D, chi, modes, args):
     zero-padded to D and gauged with seeded random invertible matrices on
     every bond (seed 1234), so that most of the cut matrix's singular values
     sit at rounding level.  Timed like the random case, in every mode the
-    random case ran; `within_1e-8` names the modes whose kappa and <H_bond>
-    stay within 1e-8 of FP64 here."""
+    random case ran, after args.structured_converge converging sweeps;
+    `within_1e-8` names the modes whose kappa and <H_bond> both stay within
+    1e-8 of FP64 here, `kappa_within_1e-8` those whose kappa does."""
     A0, B0 = synth.honeycomb_ising_tensors(0.6, 0.6, 0.6)
     A, B = synth.pad_and_gauge(A0, B0, D, 1234)
+    conv = args.structured_converge
     res = {"workload": "honeycomb Ising state, K=0.6 on every bond, padded from D=2 to D=%d and "
                        "gauged (seed 1234), chi=%d, %d sweeps after %d converging" % (
-                           D, chi, args.steps, args.converge)}
-    runs = {m: run_mode(ctx, ctm, torch, A, B, H, D, chi, m, args) for m in modes}
+                           D, chi, args.steps, conv)}
+    runs = {m: run_mode(ctx, ctm, torch, A, B, H, D, chi, m, args, converge=conv) for m in modes}
     ref = runs[0]
     for m, r in runs.items():
         res[MODE_NAMES[m]] = {"gflops": round(r["gflops"], 2), "ms_per_move": round(r["ms_per_move"], 3),
                               "ms_per_move_median": round(r["ms_per_move_median"], 3),
                               "kappa": r["kappa"], "energy_bond": r["energy_bond"],
                               "err_kappa_vs_fp64": abs(r["kappa"] / ref["kappa"] - 1.0),
-                              "err_energy_vs_fp64": abs(r["energy_bond"] - ref["energy_bond"])}
+                              "err_energy_vs_fp64": abs(r["energy_bond"] - ref["energy_bond"]),
+                              "delta_last_sweep": r["delta_last_sweep"],
+                              "self_change_kappa": r["self_change_kappa"],
+                              "self_change_energy": r["self_change_energy"]}
     res["within_1e-8"] = [MODE_NAMES[m] for m in runs if m != 0 and
                           max(res[MODE_NAMES[m]]["err_kappa_vs_fp64"],
                               res[MODE_NAMES[m]]["err_energy_vs_fp64"]) <= 1e-8]
+    res["kappa_within_1e-8"] = [MODE_NAMES[m] for m in runs if m != 0 and
+                                res[MODE_NAMES[m]]["err_kappa_vs_fp64"] <= 1e-8]
+    res["_errs"] = {m: (res[MODE_NAMES[m]]["err_kappa_vs_fp64"],
+                        res[MODE_NAMES[m]]["err_energy_vs_fp64"]) for m in runs}
     return res
 
 
@@ -287,10 +328,28 @@ def run_batch(ctm, torch, synth, count, warm, steps, uniform=None):
         out[name] = {"value": round(work * steps / dt / 1e9, 2),
                      "ms_per_batch_sweep": round(1e3 * dt / steps, 3)}
         log("bench: batch %s %s: %.1f ms per batch sweep" % (what, name, 1e3 * dt / steps))
+        if name == "in_turn":
+            kappas = [e.norm() for e in envs]
         for e in envs:
             e.close()
         for c in ctxs:
             c.close()
+    # every member's environment norm against the same member run in FP64
+    # for the same number of sweeps (all variants give identical results)
+    ctxs = [ctm.Context(0) for _ in cfg]
+    envs = []
+    for i, (D, chi) in enumerate(cfg):
+        A, B = synth.random_purification(D, 778 + i, dtype=np.float32)
+        envs.append(ctm.Environment.from_purification(ctxs[i], A, B, 2, chi,
+                                                      precision=ctm.CTM_PREC_F64))
+    ctm.sweep_batch(envs, warm + steps)
+    errs = [abs(k / e.norm() - 1.0) for k, e in zip(kappas, envs)]
+    for e in envs:
+        e.close()
+    for c in ctxs:
+        c.close()
+    out["err_kappa_vs_fp64_per_env"] = [float("%.3g" % x) for x in errs]
+    out["err_kappa_vs_fp64_max"] = max(errs)
     best = max(("concurrent_autotuned_graphs", "lockstep_grouped"), key=lambda k: out[k]["value"])
     out["best"] = best
     out["speedup_vs_in_turn"] = round(out[best]["value"] / out["in_turn"]["value"], 3)
@@ -388,6 +447,33 @@ def run_xi(ctm, synth, reps):
             "ms": round(1e3 * dt, 2), "xi": xi, "eps_2_3_4": eps}
 
 
+def select_headline(runs, structured):
+    """The headline mode: the fastest reduced-precision mode whose error
+    against FP64 stays within a bound on both workloads, the tightest bound
+    of (1e-8, 1e-7) that some mode meets; FP64 itself if none does.  The
+    error is the environment norm kappa on both the random and the
+    structured workload, and <H_bond> on the random one (the metric's
+    workload).  On the structured workload <H_bond> is reported but not
+    gated: there FP64's own <H_bond> still moves between sweeps by more
+    than the bound (self_change_energy), and the comparison cannot resolve
+    it."""
+    rule = ("kappa within the bound of FP64 on the random and the structured workload, "
+            "<H_bond> within the bound on the random workload")
+    for tol in (1e-8, 1e-7):
+        ok = []
+        for m, r in runs.items():
+            if m == 0:
+                continue
+            errs = [r["err_kappa_vs_fp64"], r["err_energy_vs_fp64"]]
+            if structured is not None:
+                errs.append(structured["_errs"][m][0])
+            if max(errs) <= tol:
+                ok.append(m)
+        if ok:
+            return min(ok, key=lambda m: runs[m]["ms_per_move"]), tol, rule
+    return 0, 0.0, rule
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,6 +492,8 @@ def main():
                     help="timed calls of the full-update measurement (0: skip it)")
     ap.add_argument("--structured", type=int, default=1,
                     help="also time the structured (padded honeycomb Ising) case (0: skip it)")
+    ap.add_argument("--structured-converge", type=int, default=40,
+                    help="untimed sweeps of the structured case before warmup")
     ap.add_argument("--modes", default="0,1,3,4",
                     help="precision modes to time (0 FP64, 1 FP32, 3/4 BF16 slices); FP64 always runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -439,18 +527,10 @@ def main():
         r["err_kappa_vs_fp64"] = abs(r["kappa"] / ref["kappa"] - 1.0)
         r["err_energy_vs_fp64"] = abs(r["energy_bond"] - ref["energy_bond"])
         r["speedup_vs_fp64"] = ref["ms_per_move"] / r["ms_per_move"]
-    # headline: the fastest reduced-precision mode whose kappa and <H_bond>
-    # stay within 1e-8 of FP64; if none does, the fastest within 1e-7
-    head, bound = None, None
-    for tol in (1e-8, 1e-7):
-        ok = [m for m in runs if m != ctm.CTM_PREC_F64 and
-              max(runs[m]["err_kappa_vs_fp64"], runs[m]["err_energy_vs_fp64"]) <= tol]
-        if ok:
-            head = min(ok, key=lambda m: runs[m]["ms_per_move"])
-            bound = tol
-            break
-    if head is None:
-        head, bound = ctm.CTM_PREC_F64, 0.0
+    structured = None
+    if args.structured:
+        structured = run_structured(ctx, ctm, torch, synth, H, D, chi, modes, args)
+    head, bound, rule = select_headline(runs, structured)
     h = runs[head]
     dtype = MODE_NAMES[head]
 
@@ -474,8 +554,14 @@ def main():
                    "step": "one sweep = 4 absorption moves (L, R, U, D)"},
         "ms_per_move": round(h["ms_per_move"], 3),
         "error_bound_vs_fp64": bound,
+        "headline_rule": rule,
         "err_kappa_vs_fp64": h["err_kappa_vs_fp64"],
         "err_energy_vs_fp64": h["err_energy_vs_fp64"],
+        "structured_err_kappa_vs_fp64": (None if structured is None else
+                                         structured[dtype]["err_kappa_vs_fp64"]),
+        "structured_err_energy_vs_fp64": (None if structured is None else
+                                          structured[dtype]["err_energy_vs_fp64"]),
+        "executed_gflops": round(h["executed_gflops"], 2),
         "mixed_vs_fp64_speedup": round(h["speedup_vs_fp64"], 3),
         "fp64": {"value": round(ref["gflops"], 2), "ms_per_move": round(ref["ms_per_move"], 3),
                  "pct_fp64_mfma_peak_algorithmic": round(100.0 * ref["gflops"] / (PEAK_F64_TFLOPS * 1e3), 2),
@@ -490,8 +576,9 @@ def main():
         "kappa": h["kappa"],
         "energy_bond": h["energy_bond"],
     }
-    if args.structured:
-        out["structured"] = run_structured(ctx, ctm, torch, synth, H, D, chi, modes, args)
+    if structured is not None:
+        structured.pop("_errs")
+        out["structured"] = structured
     if args.batch > 0:
         out["batch"] = run_batch(ctm, torch, synth, args.batch, 3, 2)
         out["batch_uniform"] = run_batch(ctm, torch, synth, args.batch, 3, 4, uniform=(4, 32))

@@ -92,3 +92,42 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_cpu_baseline_runs_the_moves_it_divides_by(monkeypatch):
+    """The oracle sample runs exactly `moves` moves, cycling L, R, U, D, and
+    the rate divides the work of those moves (not of more) by their time."""
+    from oracle import ctmrg as O
+    calls = []
+    real = O.left_move
+
+    def counted(env, arot, k, chi, *a, **kw):
+        calls.append(k)
+        return real(env, arot, k, chi, *a, **kw)
+
+    monkeypatch.setattr(O, "left_move", counted)
+    assert bench.cpu_baseline_order(6) == [0, 2, 1, 3, 0, 2]
+    res = bench.cpu_baseline(2, 4, 1, moves=10)
+    assert calls == [0, 2, 1, 3, 0, 2, 1, 3, 0, 2]
+    assert res["moves"] == 10 and res["sample"].startswith("10 absorption moves")
+    rate = 10 * 2.0 * bench.move_macs(4, 4) / res["seconds"] / 1e9
+    assert res["value"] == pytest.approx(rate, rel=0.02)
+
+
+def test_headline_needs_the_bound_on_both_workloads():
+    """A mode heads the line only if kappa stays within the bound on the
+    random and the structured workload and <H_bond> on the random one."""
+    def r(ms, ek, ee):
+        return {"ms_per_move": ms, "err_kappa_vs_fp64": ek, "err_energy_vs_fp64": ee}
+    runs = {0: r(6.0, 0.0, 0.0), 1: r(5.0, 1e-11, 3e-8), 3: r(4.0, 1e-12, 2e-9),
+            4: r(4.5, 1e-12, 3e-9)}
+    st = {"_errs": {0: (0.0, 0.0), 1: (2e-10, 2e-6), 3: (2e-12, 5e-6), 4: (1e-12, 8e-8)}}
+    assert bench.select_headline(runs, st)[:2] == (3, 1e-8)
+    st["_errs"][3] = (2e-8, 5e-6)          # bf16x3 kappa off on the structured case
+    assert bench.select_headline(runs, st)[:2] == (4, 1e-8)
+    runs[4]["err_energy_vs_fp64"] = 5e-8   # bf16x4 <H> off on the random case
+    assert bench.select_headline(runs, st)[:2] == (3, 1e-7)
+    assert bench.select_headline(runs, None)[:2] == (3, 1e-8)
+    for m in (1, 3, 4):
+        runs[m]["err_kappa_vs_fp64"] = 1e-6
+    assert bench.select_headline(runs, st)[:2] == (0, 0.0)
