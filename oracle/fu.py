@@ -15,6 +15,9 @@ Fig. 4):
      d(A'', B'') = sum_p <K'(p) - K''(p), E (K'(p) - K''(p))>,
    K = composite over the gamma bond, p its pseudospin and ancilla index.
 
+Every multi-operand contraction is one ``numpy.einsum`` of its defining
+expression, evaluated pairwise (``optimize=True``).
+
 Readings (the paper gives the objective, not the optimiser):
   * the minimisation alternates exact least-squares solves for A'' with B''
     fixed and for B'' with A'' fixed (alternating least squares), starting
@@ -56,16 +59,16 @@ def composite_matrix(Ap, Bp):
 def metric_error(Kt, K, E):
     """sum_p <Kt_p - K_p, E (Kt_p - K_p)>."""
     dK = Kt - K
-    return float(np.einsum('pi,ij,pj->', dK, E, dK))
+    return float(np.einsum('pi,ij,pj->', dK, E, dK, optimize=True))
 
 
 def als_update_A(Kp, E, Bp, D):
     """Least-squares A'' for fixed B'' in the metric E (4 right-hand sides)."""
     Dg = Bp.shape[4]
     E4 = E.reshape(D, D, D, D, D, D, D, D)  # u l d r | u' l' d' r'
-    N = np.einsum('tcrdg,uldrvmef,tcfeh->lugmvh', Bp, E4, Bp).reshape(D * D * Dg, D * D * Dg)
+    N = np.einsum('tcrdg,uldrvmef,tcfeh->lugmvh', Bp, E4, Bp, optimize=True).reshape(D * D * Dg, D * D * Dg)
     K4 = Kp.reshape(2, 2, 2, 2, D, D, D, D)  # s a t c u l d r
-    b = np.einsum('tcrdg,uldrvmef,satcvmef->salug', Bp, E4, K4).reshape(4, D * D * Dg)
+    b = np.einsum('tcrdg,uldrvmef,satcvmef->salug', Bp, E4, K4, optimize=True).reshape(4, D * D * Dg)
     N = N + RIDGE * np.trace(N) / N.shape[0] * np.eye(N.shape[0])
     X = np.linalg.solve(N, b.T)
     return X.T.reshape(2, 2, D, D, Dg)
@@ -75,9 +78,9 @@ def als_update_B(Kp, E, Ap, D):
     """Least-squares B'' for fixed A'' in the metric E."""
     Dg = Ap.shape[4]
     E4 = E.reshape(D, D, D, D, D, D, D, D)
-    N = np.einsum('salug,uldrvmef,samvh->rdgfeh', Ap, E4, Ap).reshape(D * D * Dg, D * D * Dg)
+    N = np.einsum('salug,uldrvmef,samvh->rdgfeh', Ap, E4, Ap, optimize=True).reshape(D * D * Dg, D * D * Dg)
     K4 = Kp.reshape(2, 2, 2, 2, D, D, D, D)
-    b = np.einsum('salug,uldrvmef,satcvmef->tcrdg', Ap, E4, K4).reshape(4, D * D * Dg)
+    b = np.einsum('salug,uldrvmef,satcvmef->tcrdg', Ap, E4, K4, optimize=True).reshape(4, D * D * Dg)
     N = N + RIDGE * np.trace(N) / N.shape[0] * np.eye(N.shape[0])
     X = np.linalg.solve(N, b.T)
     return X.T.reshape(2, 2, D, D, Dg)
@@ -92,7 +95,7 @@ def truncate(Ap_gated, Bp_gated, E, A0p, B0p, als_iters):
     D = A0p.shape[2]
     Kp = composite_matrix(Ap_gated, Bp_gated)
     Es = 0.5 * (E + E.T)
-    norm = float(np.einsum('pi,ij,pj->', Kp, Es, Kp))
+    norm = float(np.einsum('pi,ij,pj->', Kp, Es, Kp, optimize=True))
     Ap, Bp = A0p.copy(), B0p.copy()
     errs = [metric_error(Kp, composite_matrix(Ap, Bp), Es) / norm]
     for _ in range(als_iters):

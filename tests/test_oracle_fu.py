@@ -65,3 +65,37 @@ def test_trotter_step_with_only_z_bonds_is_one_z_update():
     A2, B2, _, _ = fu.bond_update(A, B, 2, Hz, 0.3, 8, 5, 3)
     K1, K2 = O.composite(A1, B1, 2), O.composite(A2, B2, 2)
     assert np.abs(K1 - K2).max() < 1e-9 * np.abs(K2).max()
+
+
+def _only(gamma, H):
+    Z = np.zeros((4, 4))
+    return [H if g == gamma else Z for g in range(3)]
+
+
+def test_trotter_step_x_and_y_fractions_and_order():
+    """Sec. III: the second-order step is G_x(db/2) G_y(db/2) G_z(db) G_y(db/2)
+    G_x(db/2).  With only x terms the y and z gates are the identity (which a
+    bond update keeps exactly), so the step is two x updates of db/2 each, at
+    the first and last positions; with only y terms it is two y updates of
+    db/2 at the second and fourth positions.  A wrong fraction (db instead
+    of db/2, or db/2 once) or a wrong position fails here, because a bond
+    update with truncation is not additive in tau."""
+    D, db = 2, 0.6
+    A, B = synth.random_purification(D, 13)
+    H = synth.bond_operator_real(synth.random_coefficients(14))
+    for gamma, where in ((0, (0, 4)), (1, (1, 3))):
+        A1, B1, hist = fu.trotter_step(A, B, _only(gamma, H), db, 8, 5, 3)
+        Ah, Bh, _, _ = fu.bond_update(A, B, gamma, H, 0.5 * db, 8, 5, 3)
+        A2, B2, _, _ = fu.bond_update(Ah, Bh, gamma, H, 0.5 * db, 8, 5, 3)
+        K1, K2 = O.composite(A1, B1, gamma), O.composite(A2, B2, gamma)
+        assert np.abs(K1 - K2).max() < 1e-9 * np.abs(K2).max()
+        # the gates of the other bond types are the identity: no error there
+        for i in range(5):
+            if i in where:
+                assert hist[i][0] > 1e-8
+            else:
+                assert hist[i][0] < 1e-20
+        # one full-db update is a different tensor: the fraction is pinned
+        Af, Bf, _, _ = fu.bond_update(A, B, gamma, H, db, 8, 5, 3)
+        Kf = O.composite(Af, Bf, gamma)
+        assert np.abs(K1 - Kf).max() > 1e-6 * np.abs(Kf).max()

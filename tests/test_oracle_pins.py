@@ -324,3 +324,43 @@ def test_corner_spectra_depend_on_svd_routine():
     assert np.linalg.norm(E1 - E2) / np.linalg.norm(E1) < 1e-10
     ds = np.abs(np.array(O.corner_spectra(env1)) - np.array(O.corner_spectra(env2))).max()
     assert 1e-10 < ds < 2e-8
+
+
+def test_bond_metric_layout_against_a_brute_force_3x3_overlap():
+    """The bond metric's layout, ket legs then bra legs (Sec. III, last
+    paragraph: the environment of the fused bond as a map from ket to bra).
+    In a double layer of one state ket and bra are interchangeable, so the
+    pin uses the overlap network of two different composites, ket K1 and bra
+    K2, whose metric is not symmetric.  One untruncated sweep from the
+    boundary start represents the 3 x 3 open lattice exactly; its metric is
+    compared with the eight neighbours of the centre contracted directly
+    (every outer leg closed with vec(I_D)), with each fused leg split as
+    (ket, bra) = (k, b) of index k * D + b."""
+    D = 2
+    A1, B1 = synth.random_purification(D, 41)
+    A2, B2 = synth.random_purification(D, 42)
+    K1, K2 = O.composite(A1, B1), O.composite(A2, B2)
+    a = np.einsum('pulvr,pxyzw->uxlyvzrw', K1, K2).reshape(D * D, D * D, D * D, D * D)
+    bv = O.boundary_vector_double_layer(D)
+    env, _ = O.ctmrg(a, 16, bv, 1)
+    E8 = O.bond_metric(env, a, D)
+    # brute force: rows top to bottom, the centre (1, 1) left open
+    Ebf = np.einsum('u,l,ulxy->xy', bv, bv, a)                    # (0,0): d=x1 r=y1
+    Ebf = np.einsum('xy,u,uyUz->xUz', Ebf, bv, a)                 # (0,1): l=y1 d=U r=y2
+    Ebf = np.einsum('xUz,zwr,r->xUw', Ebf, np.einsum('uzwr,u->zwr', a, bv), bv)  # (0,2): d=x3
+    Ebf = np.einsum('xUw,xlpL,l->UwpL', Ebf, a, bv)               # (1,0): u=x1 d=x4 r=L
+    Ebf = np.einsum('UwpL,wRqr,r->UpLRq', Ebf, a, bv)             # (1,2): u=x3 l=R d=x5
+    Ebf = np.einsum('UpLRq,plds,l,d->ULRqs', Ebf, a, bv, bv)      # (2,0): u=x4 r=y6
+    Ebf = np.einsum('ULRqs,Vsdt,d->ULRqVt', Ebf, a, bv)           # (2,1): u=V l=y6 r=y7
+    Ebf = np.einsum('ULRqVt,qtdr,d,r->ULVR', Ebf, a, bv, bv)      # (2,2): u=x5 l=y7
+    Ebf = Ebf / np.einsum('ulxr,ulxr->', Ebf, a)
+    ref = Ebf.reshape((D,) * 8).transpose(0, 2, 4, 6, 1, 3, 5, 7)
+    assert np.abs(ref.reshape(D ** 4, D ** 4) - ref.reshape(D ** 4, D ** 4).T).max() > 1e-3 * np.abs(ref).max()
+    # (the projectors of the untruncated sweep are exact up to the rounding of
+    # the cut matrices' small singular values)
+    assert np.abs(E8 - ref).max() < 1e-10 * np.abs(ref).max()
+    # the defining contraction: K1 on the ket side, K2 on the bra side
+    Em = E8.reshape(D ** 4, D ** 4)
+    k1, k2 = K1.reshape(16, D ** 4), K2.reshape(16, D ** 4)
+    assert abs(np.einsum('pk,kb,pb->', k1, Em, k2) - 1.0) < 1e-10
+    assert abs(np.einsum('pk,kb,pb->', k2, Em, k1) - 1.0) > 1e-3
