@@ -56,8 +56,7 @@ extern "C" {
 #define CTM_PREC_F32     1  /* one FP32 MFMA product, FP64 storage */
 #define CTM_PREC_BF16X3  3  /* FP64 operands split into 3 BF16 slices */
 #define CTM_PREC_BF16X4  4  /* ... 4 slices */
-#define CTM_PREC_BF16X5  5  /* ... 5 slices */
-#define CTM_PREC_BF16X6  6  /* ... 6 slices */
+/* Any other value (2, 5, 6, ...) is rejected with CTM_EINVAL. */
 
 typedef struct ctm_context ctm_context;
 typedef struct ctm_env ctm_env;
@@ -66,8 +65,10 @@ typedef struct ctm_opts {
   int precision;          /* CTM_PREC_*; default CTM_PREC_F64 */
   double eps_cut;         /* singular values below eps_cut * s_1 get S^-1/2 := 0
                              (shapes kept); default 1e-12 */
-  int svd_block;          /* subspace size b >= chi of the truncated projector
-                             SVD; 0 = automatic (min(chi*d, 96)) */
+  int svd_block;          /* subspace size b (chi <= b <= 128) of the truncated
+                             projector SVD; 0 = automatic (see svd_oversample).
+                             A cut matrix with chi*d <= 128 rows gets a full
+                             Jacobi SVD instead. */
   int svd_iters;          /* subspace iterations per move when warm-started;
                              0 = automatic (2) */
   int svd_iters_cold;     /* iterations from a random start; 0 = automatic (5) */
@@ -76,6 +77,22 @@ typedef struct ctm_opts {
   const double* boundary; /* length-d boundary vector of the initial edges, or
                              NULL: e_0 for ctm_env_init_tensor, vec(I_D) for
                              ctm_env_init_purification */
+  int svd_oversample;     /* with svd_block = 0: b = min(chi*d, chi + svd_oversample,
+                             128); 0 = automatic, b = min(chi*d, max(96, chi + 24),
+                             128) */
+  double svd_tol;         /* > 0: after each truncated SVD's fixed iterations, iterate
+                             again from its vectors (at most 8 more times) until
+                             max_i ||M u_i - s_i v_i|| / s_1 over the kept chi
+                             triplets is at most svd_tol; every check waits for
+                             the device, so such sweeps are never replayed from
+                             graphs.  < 0: fixed iteration counts only.  0 =
+                             automatic: fixed counts for sweeps, 1e-12 for the
+                             gradient calls (the adjoint assumes exact SVDs). */
+  int move_order[4];      /* directions of the four moves of a sweep, a permutation
+                             of 0 (left), 1 (up), 2 (right), 3 (down): the move in
+                             direction k is the left move of the lattice rotated
+                             k times by 90 degrees.  All zero = default
+                             {0, 2, 1, 3}: left, right, up, down. */
 } ctm_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -237,6 +254,15 @@ int ctm_env_load(ctm_env* env, const char* path);
 
 /* Shape queries. */
 int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps);
+
+/* Accuracy of the truncated projector SVD (Sec. III, the CTMRG truncation
+ * of Fig. 4(c)).  calls: truncated SVDs computed by subspace iteration so far
+ * (cut matrices of at most 128 rows get a full Jacobi SVD and are not
+ * counted); iterations: their subspace iterations in total; last_residual:
+ * max_i ||M u_i - s_i v_i|| / s_1 over the kept chi triplets of the last
+ * move's cut matrix M (0 before the first move), computed on request, which
+ * waits for the device.  Any pointer may be NULL. */
+int ctm_svd_stats(ctm_env* env, long long* calls, long long* iterations, double* last_residual);
 
 /* Statistics of the last gradient call. */
 typedef struct ctm_grad_info {

@@ -376,7 +376,7 @@ void Grad::run_segment(int sg, bool record) {
   for (int s = s0; s < s1; ++s) {
     for (int i = 0; i < 4; ++i) {
       e.tape_slot = record ? tape.d() + (size_t)m * tl.total : nullptr;
-      e.move(kSweepOrder[i]);
+      e.move(e.opt.move_order[i]);
       ++m;
     }
     e.tape_slot = nullptr;
@@ -857,7 +857,7 @@ void Grad::backward() {
     }
     const int s0 = sg * every, s1 = std::min(sweeps, s0 + every);
     const int nm = 4 * (s1 - s0);
-    for (int m = nm - 1; m >= 0; --m) move_bwd(kSweepOrder[m & 3], tape.d() + (size_t)m * tl.total);
+    for (int m = nm - 1; m >= 0; --m) move_bwd(e.opt.move_order[m & 3], tape.d() + (size_t)m * tl.total);
   }
   CTM_HIP(hipStreamSynchronize(ctx.stream));
   stats.ms_recompute = trec;

@@ -108,15 +108,40 @@ ctm::EnvOptions to_options(const ctm_opts* o, int d) {
   r.svd_block = o->svd_block;
   r.svd_iters = o->svd_iters;
   r.svd_iters_cold = o->svd_iters_cold;
+  r.svd_oversample = o->svd_oversample;
+  CTM_REQUIRE(o->svd_oversample >= 0, "svd_oversample must be >= 0");
+  CTM_REQUIRE(!(o->svd_tol != o->svd_tol), "svd_tol must not be NaN");
+  r.svd_tol = o->svd_tol;
+  const int* mo = o->move_order;
+  if (mo[0] || mo[1] || mo[2] || mo[3]) {
+    int seen = 0;
+    for (int i = 0; i < 4; ++i) {
+      CTM_REQUIRE(mo[i] >= 0 && mo[i] < 4, "move_order entries must be 0..3");
+      seen |= 1 << mo[i];
+    }
+    CTM_REQUIRE(seen == 15, "move_order must be a permutation of 0, 1, 2, 3");
+    for (int i = 0; i < 4; ++i) r.move_order[i] = mo[i];
+  }
   r.seed = o->seed;
   if (o->boundary) r.boundary.assign(o->boundary, o->boundary + d);
   return r;
 }
 
 void check_precision(int p) {
-  if (p != CTM_PREC_F64 && p != CTM_PREC_F32 && !(p >= CTM_PREC_BF16X3 && p <= CTM_PREC_BF16X6))
-    throw ctm::Error(CTM_EINVAL, "unknown precision mode");
-  if (!ctm::mixed_mode_supported(p)) throw ctm::Error(CTM_EINVAL, "precision mode not available");
+  if (!ctm::mixed_mode_supported(p)) throw ctm::Error(CTM_EINVAL, "unknown precision mode");
+}
+
+// The adjoint differentiates the exact top-chi SVD of every cut matrix, so
+// the forward's truncated SVD is iterated to this residual unless the caller
+// sets svd_tol (a negative value keeps the fixed iteration counts).
+constexpr double kGradSvdTol = 1e-12;
+
+ctm::EnvOptions gradient_options(const ctm_opts* opts, int d) {
+  ctm::EnvOptions o = to_options(opts, d);
+  check_precision(o.precision);
+  CTM_REQUIRE(o.precision == CTM_PREC_F64, "gradients need precision CTM_PREC_F64");
+  if (o.svd_tol == 0.0) o.svd_tol = kGradSvdTol;
+  return o;
 }
 
 }  // namespace
@@ -132,6 +157,9 @@ void ctm_opts_default(ctm_opts* o) {
   o->svd_iters_cold = 0;
   o->seed = 0x5eedULL;
   o->boundary = nullptr;
+  o->svd_oversample = 0;
+  for (int i = 0; i < 4; ++i) o->move_order[i] = 0;
+  o->svd_tol = 0.0;
 }
 
 int ctm_context_create(int device, ctm_context** out) {
@@ -425,9 +453,7 @@ int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, in
     CTM_REQUIRE(op || w_expect == 0.0, "w_expect needs an operator");
     CTM_REQUIRE(!op || op_dim == 4 || op_dim == 16, "op_dim must be 4 or 16");
     const int d = D * D;
-    ctm::EnvOptions o = to_options(opts, d);
-    check_precision(o.precision);
-    CTM_REQUIRE(o.precision == CTM_PREC_F64, "gradients need precision CTM_PREC_F64");
+    ctm::EnvOptions o = gradient_options(opts, d);
     CTM_HIP(hipSetDevice(ctx->c.device));
     ctm::Env env(ctx->c, d, chi, o);
     const size_t sz = 4ull * D * D * D_gamma;
@@ -460,9 +486,7 @@ int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm
     CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
     CTM_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
     CTM_REQUIRE(a_imp || w_expect == 0.0, "w_expect needs an impurity tensor");
-    ctm::EnvOptions o = to_options(opts, d);
-    check_precision(o.precision);
-    CTM_REQUIRE(o.precision == CTM_PREC_F64, "gradients need precision CTM_PREC_F64");
+    ctm::EnvOptions o = gradient_options(opts, d);
     CTM_HIP(hipSetDevice(ctx->c.device));
     ctm::Env env(ctx->c, d, chi, o);
     const size_t d4 = (size_t)d * d * d * d;
@@ -606,13 +630,14 @@ int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, dou
       std::vector<ctm::GroupProblem> first[3], second[3];  // by kernel kind 1, 2
       for (int s = 0; s < max_sweeps; ++s) {
         for (int m = 0; m < 4; ++m) {
-          const int k = ctm::kSweepOrder[m];
+          // move m of every environment's own sweep order
           for (auto& v : first) v.clear();
           for (auto& v : second) v.clear();
           for (int i = 0; i < count; ++i) {
             if (!active[i]) continue;
             cur = i;
             ctm::Env& e = *envs[i]->e;
+            const int k = e.opt.move_order[m];
             e.move_front(k);
             kind[i] = e.cut_products(k, &probs[3 * (size_t)i]);
             if (kind[i] == 0) continue;
@@ -636,6 +661,7 @@ int ctm_sweep_batch_grouped(ctm_env* const* envs, int count, int max_sweeps, dou
             if (!active[i]) continue;
             cur = i;
             ctm::Env& e = *envs[i]->e;
+            const int k = e.opt.move_order[m];
             if (kind[i] == 0) e.move_products(k);
             else CTM_HIP(hipStreamWaitEvent(envs[i]->owner_c->stream, evg, 0));
             e.move_back(k);
@@ -797,6 +823,16 @@ int ctm_env_load(ctm_env* env, const char* path) {
     CTM_REQUIRE(f.good(), "truncated checkpoint file");
     e.set(C.data(), T.data(), L.data());
     e.sweeps_done = hdr[3];
+  });
+}
+
+int ctm_svd_stats(ctm_env* env, long long* calls, long long* iterations, double* last_residual) {
+  if (!env) return CTM_EINVAL;
+  return guarded_c(env->owner_c, [&] {
+    CTM_HIP(hipSetDevice(env->owner_c->device));
+    if (calls) *calls = env->e->svd_calls;
+    if (iterations) *iterations = env->e->svd_iterations;
+    if (last_residual) *last_residual = env->e->last_svd_residual();
   });
 }
 

@@ -28,6 +28,10 @@ namespace ctm {
 
 namespace {
 
+// Largest number of iterations a tolerance-controlled truncated SVD adds
+// after the fixed ones.
+constexpr int kSvdMaxExtraIters = 8;
+
 __global__ void add_log_slots_kernel(double* logs, int dst0, int src0, int dst1, int src1) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     logs[dst0] += logs[src0];
@@ -45,20 +49,29 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
   const int bmax = jacobi_max_b(true);
   if (n <= bmax) {
     b = n;  // the cut matrix is small enough for a direct Jacobi SVD
+  } else if (opt.svd_block > 0) {
+    CTM_REQUIRE(opt.svd_block >= chi && opt.svd_block <= bmax,
+                "svd_block must lie between chi and 128");
+    b = std::min(opt.svd_block, n);
   } else {
-    b = opt.svd_block > 0 ? opt.svd_block : bmax;
+    // the chi kept directions plus a margin that separates them from the
+    // rest of the spectrum during the subspace iteration
+    const int over = opt.svd_oversample > 0 ? opt.svd_oversample : 0;
+    b = over > 0 ? chi + over : std::max(96, chi + 24);
     b = std::min(b, std::min(n, bmax));
-    CTM_REQUIRE(b >= chi, "svd_block must be >= chi and <= 96 (chi <= 96 with a chi*d > 96 cut)");
   }
   if (opt.svd_iters <= 0) opt.svd_iters = 2;
   if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 5;
   alloc();
   CTM_HIP(hipHostMalloc((void**)&hbox, 64, hipHostMallocDefault));
+  CTM_HIP(hipHostMalloc((void**)&hres, (std::max(chi, b) + 2) * sizeof(double),
+                        hipHostMallocDefault));
 }
 
 Env::~Env() {
   drop_graph();
   if (hbox) (void)hipHostFree(hbox);
+  if (hres) (void)hipHostFree(hres);
 }
 
 void Env::drop_graph() {
@@ -98,7 +111,7 @@ void Env::alloc() {
   for (int i = 0; i < 4; ++i) warm[i].alloc(nb * sizeof(double));
   G.alloc((size_t)b * b * sizeof(double));
   Wm.alloc((size_t)b * b * sizeof(double));
-  Bsm.alloc((size_t)std::max(b * b, n * n <= 96 * 96 ? n * n : 1) * sizeof(double));
+  Bsm.alloc((size_t)b * b * sizeof(double));
   xs.alloc((size_t)b * b * sizeof(double));
   ys.alloc((size_t)b * b * sizeof(double));
   sv.alloc((size_t)std::max(b, chi) * sizeof(double));
@@ -117,6 +130,7 @@ void Env::alloc() {
   fill_zero(ctx, (double*)rngc.p, 2);
   E.alloc(dd4 * sizeof(double));
   E8.alloc(dd4 * sizeof(double));
+  resid.alloc((size_t)(std::max(chi, b) + 2) * sizeof(double));
   fill_zero(ctx, logs.d(), 8);
   fill_zero(ctx, scal.d(), 64);
   fill_zero_int(ctx, (int*)iflags.p, 8 + b);
@@ -275,16 +289,40 @@ void Env::svd_top(const double* MtP, int k) {
     orth(Z0.d(), Om.d(), 2);
     iters = opt.svd_iters_cold;
   }
-  for (int it = 0; it < iters; ++it) {
-    // Z = Mt Om must be orthogonalised (not only normalised) before Mt^T is
-    // applied: a column carrying a small contamination of a leading
-    // direction would otherwise lose its own small-singular-value component.
-    gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
-    orth(Z0.d(), Qz.d(), 1);
-    gemm_f64(ctx, n, b, n, 1.0, colmajor(MtP, n), rowmajor(Qz.d(), b), 0.0, out_rowmajor(Z0.d(), b));
-    orth(Z0.d(), Om.d(), 2);
+  for (int it = 0; it < iters; ++it) subspace_iteration(MtP);
+  rayleigh_ritz(MtP);
+  ++svd_calls;
+  svd_iterations += iters;
+  if (opt.svd_tol > 0.0) {
+    // continue from the Ritz vectors until the kept triplets' residual meets
+    // the tolerance (each check waits for the device)
+    for (int extra = 0; extra < kSvdMaxExtraIters; ++extra) {
+      if (svd_residual(MtP) <= opt.svd_tol) break;
+      copy_dev(ctx, Om.d(), VA.d(), (size_t)n * b);
+      subspace_iteration(MtP);
+      rayleigh_ritz(MtP);
+      ++svd_iterations;
+    }
   }
-  // Rayleigh-Ritz
+  copy_dev(ctx, warm[k].d(), VA.d(), (size_t)n * b);
+  warm_ok[k] = true;
+}
+
+// One subspace iteration on Om: Z = Mt Om must be orthogonalised (not only
+// normalised) before Mt^T is applied: a column carrying a small contamination
+// of a leading direction would otherwise lose its own small-singular-value
+// component.
+void Env::subspace_iteration(const double* MtP) {
+  gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+  orth(Z0.d(), Qz.d(), 1);
+  gemm_f64(ctx, n, b, n, 1.0, colmajor(MtP, n), rowmajor(Qz.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+  orth(Z0.d(), Om.d(), 2);
+}
+
+// Rayleigh-Ritz on the subspace Om: Z = Mt Om = Qz B with B upper triangular,
+// B = x s y^T, so Mt Om = (Qz x) s y^T: UA = Qz x, VA = Om y, sv = s.
+void Env::rayleigh_ritz(const double* MtP) {
+  int* err = (int*)iflags.p + 1;
   gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
   orth(Z0.d(), Qz.d(), 2);
   gemm_f64(ctx, b, b, n, 1.0, colmajor(Qz.d(), b), rowmajor(Z0.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
@@ -292,8 +330,38 @@ void Env::svd_top(const double* MtP, int k) {
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
   fix_signs(ctx, UA.d(), b, VA.d(), b, n, b);
-  copy_dev(ctx, warm[k].d(), VA.d(), (size_t)n * b);
-  warm_ok[k] = true;
+}
+
+// max_i ||Mt^T u_i - s_i v_i|| / s_1 over the kept i < min(chi, b), read back
+// to the host (waits for the stream).  Uses Z0 as scratch.
+double Env::svd_residual(const double* MtP) {
+  const int kk = std::min(chi, b);
+  gemm_f64(ctx, n, kk, n, 1.0, colmajor(MtP, n), rowmajor(UA.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+  column_residuals(ctx, Z0.d(), VA.d(), sv.d(), n, b, kk, resid.d());
+  CTM_HIP(hipMemcpyAsync(hres, resid.p, (kk + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx.stream));
+  CTM_HIP(hipStreamSynchronize(ctx.stream));
+  double r = 0.0;
+  for (int i = 0; i < kk; ++i) r = std::max(r, hres[i]);
+  return hres[kk] > 0.0 ? r / hres[kk] : (r > 0.0 ? INFINITY : 0.0);
+}
+
+double Env::last_svd_residual() {
+  if (!moved) return 0.0;
+  if (n <= jacobi_max_b(true)) {
+    // full Jacobi SVD of the cut matrix: the same check on its triplets
+    const int kk = std::min(chi, n);
+    gemm_f64(ctx, n, kk, n, 1.0, colmajor(Mt.d(), n), rowmajor(UA.d(), b), 0.0,
+             out_rowmajor(Z0.d(), b));
+    column_residuals(ctx, Z0.d(), VA.d(), sv.d(), n, b, kk, resid.d());
+    CTM_HIP(hipMemcpyAsync(hres, resid.p, (kk + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    CTM_HIP(hipStreamSynchronize(ctx.stream));
+    double r = 0.0;
+    for (int i = 0; i < kk; ++i) r = std::max(r, hres[i]);
+    return hres[kk] > 0.0 ? r / hres[kk] : 0.0;
+  }
+  return svd_residual(Mt.d());
 }
 
 // a4 - a7: one absorption move (left move of frame k).
@@ -413,6 +481,7 @@ void Env::move_back(int k) {
   qvalid[q0] = false;
   qvalid[q3] = false;
   e_valid = false;
+  moved = true;
 }
 
 void Env::reset_spectra() {
@@ -440,7 +509,7 @@ int Env::sweep(int max_sweeps, double tol, int* done, double* delta_out) {
 
 void Env::sweep_body() {
   int* err = (int*)iflags.p + 1;
-  for (int i = 0; i < 4; ++i) move(kSweepOrder[i]);
+  for (int i = 0; i < 4; ++i) move(opt.move_order[i]);
   jacobi_svd(ctx, Call.d(), chi, nullptr, spec_s.d(), nullptr, err, 4, (long long)chi * chi, chi);
   spectra_delta(ctx, spec_s.d(), spec_old.d(), chi, scal.d());
 }
@@ -460,6 +529,7 @@ void Env::sweep_tail_eager() {
 // the capture).  Timing events are not captured.
 bool Env::graph_ready() const {
   if (!ctx.use_graphs || ctx.timing || !warm_eager_done) return false;
+  if (opt.svd_tol > 0.0) return false;  // its residual checks wait for the device
   if (n > jacobi_max_b(true))
     for (int k = 0; k < 4; ++k)
       if (!warm_ok[k]) return false;

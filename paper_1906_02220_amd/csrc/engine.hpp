@@ -5,15 +5,18 @@
 
 namespace ctm {
 
-// Move directions of one sweep: left, right, up, down.
-constexpr int kSweepOrder[4] = {0, 2, 1, 3};
-
 struct EnvOptions {
   int precision = 0;
   double eps_cut = 1e-12;
   int svd_block = 0;
   int svd_iters = 0;
   int svd_iters_cold = 0;
+  int svd_oversample = 0;
+  // > 0: after the Rayleigh-Ritz step, iterate again (from its vectors) until
+  // the largest residual ||Mt^T u_i - s_i v_i|| / s_1 of the kept triplets is
+  // at most svd_tol; <= 0: the fixed iteration counts only
+  double svd_tol = 0.0;
+  int move_order[4] = {0, 2, 1, 3};  // directions of a sweep: left, right, up, down
   unsigned long long seed = 0x5eedULL;
   std::vector<double> boundary;  // empty: default
 };
@@ -91,6 +94,11 @@ class Env {
   void corner_spectra(double* host_out, size_t len);
   void get(double* C, double* T, double* logs);
   void set(const double* C, const double* T, const double* logs);
+  // max_i ||Mt^T u_i - s_i v_i|| / s_1 over the kept triplets of the last
+  // move's truncated SVD (0 before the first move)
+  double last_svd_residual();
+  // truncated SVDs by subspace iteration so far and their iterations
+  long long svd_calls = 0, svd_iterations = 0;
 
   Context& ctx;
   int d, chi, n;
@@ -109,6 +117,9 @@ class Env {
   void drop_graph();
   void corner(int f);
   void svd_top(const double* Mt, int k);
+  void subspace_iteration(const double* Mt);
+  void rayleigh_ritz(const double* Mt);
+  double svd_residual(const double* Mt);
   void orth(double* Z, double* Q, int passes);
   void ring();
   void reset_spectra();
@@ -132,6 +143,9 @@ class Env {
   DevBuf spec_s, spec_old, scal;  // scal: delta and observables scalars
   DevBuf iflags;                  // [0] numeric, [1] svd, [2..] dependency flags
   DevBuf E, E8;
+  DevBuf resid;                   // column residuals of the truncated SVD, then s_1
+  double* hres = nullptr;         // pinned host copy of resid
+  bool moved = false;             // a move has run: Mt, UA, VA, sv are its own
   bool e_valid = false;
   unsigned long long rng_ctr = 0;  // counter of the cold-start draws
   DevBuf rngc;                     // two device slots of the refill counter

@@ -90,6 +90,7 @@ struct Context {
   DevBuf splitk_ws;     // split-K partial products
   DevBuf mixed_ws;      // operand slices and scales of the reduced-precision GEMMs
   DevBuf scratch_small; // reductions and flags
+  DevBuf jacobi_ws;     // rotation log, ranks and sweep count of the Jacobi SVD
   Context() = default;
   Context(const Context&) = delete;
   Context& operator=(const Context&) = delete;
@@ -268,9 +269,10 @@ void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* 
 void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* dep,
                     unsigned long long seed, const unsigned long long* counter_in,
                     unsigned long long* counter_out);
-// One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T,
+// One-sided Jacobi SVD of a b x b row-major matrix B = X diag(s) Y^T (b <= 128),
 // singular values sorted descending.  X and Y (b x b row-major) may be null
-// when only the values are wanted.  batch matrices at stride bstride.  With
+// when only the values are wanted; vectors are computed for one matrix per
+// call (batch = 1), values for batch matrices at stride bstride.  With
 // trans the rotations act on the columns of B^T (faster for a graded upper
 // triangular B).  *err = 1 if the sweeps did not converge or produced
 // non-finite values.
@@ -278,6 +280,10 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
                 int batch = 1, long long bstride = 0, long long sstride = 0, bool trans = false);
 // Maximum b supported by jacobi_svd with vectors / values only.
 int jacobi_max_b(bool vectors);
+// out[i] = ||Y[:, i] - s[i] V[:, i]||_2 for i < kk (Y, V: n rows, leading
+// dimension ld, row-major), then out[kk] = s[0].
+void column_residuals(Context& ctx, const double* Y, const double* V, const double* s, int n,
+                      int ld, int kk, double* out);
 // w[j] = 1/sqrt(s[j]) if j < kk and s[j] > eps * s[0] > 0, else 0; j < chi.
 void inv_sqrt_cut(Context& ctx, const double* s, int kk, int chi, double eps, double* w);
 // Z[i][j] *= w[j] for an n x c block of a row-major matrix with leading dim ldz.

@@ -180,22 +180,22 @@ __global__ void sum_final_kernel(const double* partial, int nb, double* out) {
 // W = D^-1 X^T has Z W orthonormal.  Columns whose pivot falls below dep_tol
 // (numerically dependent) are skipped: no elimination, flag set.  All
 // updates are unconditional FMAs with masked multipliers.
-template <int TG>
+template <int NB, int TG>
 __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restrict__ G, int b,
                                                            double dep_tol, double* __restrict__ Wout,
                                                            int* __restrict__ dep, int* err) {
-  constexpr int NR = 96 / TG;
-  static_assert(NR * TG == 96, "the thread grid must tile 96");
-  static_assert(TG * TG >= 96, "threads 0..95 load the diagonal scales");
-  __shared__ double Dn[96];
-  __shared__ double rowk[2][96];
-  __shared__ double xrow[2][96];
-  __shared__ int depl[96];
+  constexpr int NR = NB / TG;
+  static_assert(NR * TG == NB, "the thread grid must tile NB");
+  static_assert(TG * TG >= NB, "threads 0..NB-1 load the diagonal scales");
+  __shared__ double Dn[NB];
+  __shared__ double rowk[2][NB];
+  __shared__ double xrow[2][NB];
+  __shared__ int depl[NB];
   __shared__ int bad;
   const int t = threadIdx.x;
   const int ti = t / TG, tj = t % TG;
   if (t == 0) bad = 0;
-  if (t < 96) {
+  if (t < NB) {
     double dv = 0.0;
     if (t < b) {
       const double g = G[t * b + t];
@@ -220,15 +220,15 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
       S[r][c] = v;
       X[r][c] = (i == j) ? 1.0 : 0.0;
     }
-  // The 96 steps are unrolled so that k, and with it the register row
+  // The NB steps are unrolled so that k, and with it the register row
   // k / TG that holds row k and the blocks the step can touch, are
   // compile-time constants: no select chains, and register blocks that lie
   // entirely before the pivot are skipped.  Row k is broadcast through a
   // double-buffered LDS row, so one barrier per step suffices (a buffer is
   // rewritten two steps later, after every reader has passed the barrier in
   // between).
-#pragma unroll 96
-  for (int k = 0; k < 96; ++k) {
+#pragma unroll NB
+  for (int k = 0; k < NB; ++k) {
     if (k >= b) continue;                                     // uniform: b is a kernel argument
     const int rk = k / TG;
     const int buf = k & 1;
@@ -303,63 +303,77 @@ __global__ void refill_kernel(double* Q, int ldq, int n, int b, const int* __res
 
 // ------------------------------------------------------------ Jacobi SVD
 
-// Sum over a group of 8 consecutive lanes (half a DPP row): butterflies
-// with quad permutations, then the half-row mirror.
-__device__ inline double dpp_step(double x, int ctrl) {
+// 64-bit DPP move: both 32-bit halves moved with the same control.
+template <int CTRL>
+__device__ inline double dpp64(double x) {
   const long long u = __double_as_longlong(x);
-  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
-  if (ctrl == 0) {
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
-  } else if (ctrl == 1) {
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
-  } else {
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
-  }
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
-__device__ inline double lane8_sum(double v) {
-  v += dpp_step(v, 0);
-  v += dpp_step(v, 1);
-  v += dpp_step(v, 2);
+// Sum over a group of LPP (8 or 16) consecutive lanes: two quad butterflies,
+// the half-row mirror and, for 16 lanes, the row mirror.
+template <int LPP>
+__device__ inline double group_sum(double v) {
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  if (LPP == 16) v += dpp64<0x140>(v);  // row_mirror
   return v;
 }
 
-// One workgroup per matrix, one-sided Jacobi (Hestenes) on the columns of A
-// (A = B, or B^T when trans != 0).  Columns of the working matrix and of V
-// are kept column-major in LDS, 8 RPT rows each, with the 8-row blocks of
-// column j permuted by block ^ (j & 3): the 8-lane groups of a wave read
-// columns whose indices differ by one, so the groups hit different banks;
-// each round of the circle
-// schedule (precomputed in LDS) rotates the bp/2 disjoint column pairs in
-// parallel, 8 lanes per pair, each lane holding RPT rows of the pair in
-// registers.  The rotation (the smaller root t of t^2 + 2 zeta t - 1 = 0,
-// c = 1/sqrt(1 + t^2), s = c t) uses Newton-refined reciprocals.  On exit
-// A = U diag(s) V^T with s descending; with trans == 0 X = U, Y = V, with
-// trans != 0 X = V, Y = U (so that always B = X diag(s) Y^T).
-// LDS row of logical row i in column j (a permutation of the 8-row blocks
-// inside each aligned group of 4 blocks).
-__device__ inline int jac_row(int i, int j) { return i ^ (8 * (j & 3)); }
+constexpr int kJacobiMaxSweeps = 60;
+constexpr int kJacobiMaxB = 128;
 
-template <int RPT>
-__global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restrict__ Bm, int b,
-                                                         long long bstride, long long sstride,
-                                                         double* __restrict__ Xo,
-                                                         double* __restrict__ so,
-                                                         double* __restrict__ Yo, int* err,
-                                                         int want_vec, int trans) {
+// Parallel (round-robin) ordering of the column pairs.  Slot g of the P = bp/2
+// slots pairs a top and a bottom column.  Slot 0's top column is column 0
+// and never moves; the other columns sit on a ring that runs through the top
+// columns of slots 1..P-1 and then the bottom columns of slots P-1..0, and
+// the ring advances one position per round, so every pair meets once in the
+// bp - 1 rounds of a sweep and a sweep ends where it began.  ring_col(k) is
+// the column at ring position k before the first round (top of slot g: 2g,
+// bottom: 2g + 1).
+__device__ inline int ring_col(int k, int P) { return k <= P - 2 ? 2 * (k + 1) : 4 * P - 3 - 2 * k; }
+
+// LDS row of logical row i in column j: 16-row (LPP = 16) or 8-row (LPP = 8)
+// blocks exchanged by j, so that the lane groups of a wave, which read
+// different columns at the same rows, start on different banks.
+template <int LPP>
+__device__ inline int jac_row(int i, int j) {
+  return i ^ (LPP * (j & (LPP == 16 ? 1 : 3)));
+}
+
+// One-sided Jacobi (Hestenes) on the columns of A (A = B, or B^T when
+// trans != 0), one workgroup per matrix.  The working matrix W = A J lives in
+// LDS, column-major, LPP * RPT rows per column; each round rotates the P
+// disjoint pairs of the ring ordering in parallel, LPP lanes per pair and RPT
+// rows per lane.  The rotation (the smaller root t of t^2 + 2 zeta t - 1 = 0,
+// c = 1/sqrt(1 + t^2), s = c t, with Newton-refined reciprocals) is applied
+// to W only: the accumulated rotations J are not kept here.  When rotlog is
+// given, the (c, s) of every slot and round go there in order ((1, 0) for a
+// pair left alone), with the number of sweeps in *sweeps_out and each
+// column's place in the descending order in rank_out, and
+// jacobi_replay_kernel rebuilds J from them.  On exit so holds the singular
+// values (the column norms of W) in descending order and Uo, if given, the
+// normalised columns of W in that order.  Sweeps stop after one whose largest
+// relative coupling |ga| / sqrt(al be) was below 1e-9: Jacobi converges
+// quadratically, so the couplings left are of order 1e-18, below the
+// rotation threshold b eps.
+template <int RPT, int LPP>
+__global__ __launch_bounds__(1024) void jacobi_kernel(
+    const double* __restrict__ Bm, int b, long long bstride, long long sstride,
+    double* __restrict__ Uo, double* __restrict__ so, double2* __restrict__ rotlog,
+    int* __restrict__ rank_out, int* __restrict__ sweeps_out, int* err, int trans) {
+  constexpr int ld = LPP * RPT;
+  static_assert(RPT % (LPP == 16 ? 2 : 4) == 0, "the row-block exchange needs whole block pairs");
   extern __shared__ double lds[];
   const int bp = b + (b & 1);
-  constexpr int ld = 8 * RPT;  // rows b..8*RPT-1 stay zero
-  static_assert(RPT % 4 == 0, "the block permutation needs groups of 4 blocks");
-  double* Wc = lds;                                  // bp columns
-  double* Vc = want_vec ? lds + bp * ld : nullptr;   // bp columns
-  double* sv = lds + (want_vec ? 2 : 1) * bp * ld;   // bp singular values
-  unsigned char* sched = (unsigned char*)(sv + bp);  // (bp-1) rounds x bp entries
+  const int P = bp / 2, m1 = bp - 1;
+  double* Wc = lds;                        // bp columns of ld rows
+  double* sv = lds + (size_t)bp * ld;      // bp column norms
+  int* rk = (int*)(sv + bp);               // bp ranks
   __shared__ int changed;
-  __shared__ int big;  // a rotated pair had |cos| of its angle above 1e-9
+  __shared__ int big;
   __shared__ int bad;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
@@ -369,46 +383,32 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
     const int j = idx / ld, i = idx - (idx / ld) * ld;
     double v = 0.0;
     if (j < b && i < b) v = trans ? B[(long long)j * b + i] : B[(long long)i * b + j];
-    const int ph = j * ld + jac_row(i, j);
-    Wc[ph] = v;
-    if (Vc) Vc[ph] = (i == j && i < b) ? 1.0 : 0.0;
-  }
-  const int P = bp / 2;
-  const int m = bp - 1;
-  for (int idx = t; idx < m * P; idx += nt) {
-    const int r = idx / P, pi = idx - (idx / P) * P;
-    int p, q;
-    if (pi == 0) { p = m; q = r; }
-    else { p = (r + pi) % m; q = (r - pi + m) % m; }
-    sched[2 * idx] = (unsigned char)p;
-    sched[2 * idx + 1] = (unsigned char)q;
+    Wc[j * ld + jac_row<LPP>(i, j)] = v;
   }
   __syncthreads();
-  const int pi = t >> 3;
-  const int sub = t & 7;
-  const bool active = pi < P;
+  const int g = t / LPP;
+  const int sub = t - g * LPP;
+  const bool active = g < P;
   const double tol = b * DBL_EPSILON;
   const double tol2 = tol * tol;
-  int sweep = 0;
-  for (; sweep < 60; ++sweep) {
-    for (int r = 0; r < m; ++r) {
+  int kp = g > 0 ? g - 1 : 0;  // ring positions of the slot's top and bottom columns
+  int kq = 2 * P - 2 - g;
+  int sweeps = 0;
+  bool converged = false;
+  while (sweeps < kJacobiMaxSweeps && !converged) {
+    for (int r = 0; r < m1; ++r) {
       if (active) {
-        const int p = sched[2 * (r * P + pi)];
-        const int q = sched[2 * (r * P + pi) + 1];
-        double* wp = Wc + p * ld + sub;
-        double* wq = Wc + q * ld + sub;
-        // offsets of the logical rows sub + 8k, k = 4g + e: 32 g + op[e]
-        int op[4], oq[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          op[e] = 8 * (e ^ (p & 3));
-          oq[e] = 8 * (e ^ (q & 3));
-        }
+        const int p = g == 0 ? 0 : ring_col(kp, P);
+        const int q = ring_col(kq, P);
+        const double* rp = Wc + p * ld + sub;
+        const double* rq = Wc + q * ld + sub;
+        const int fp = LPP * (p & (LPP == 16 ? 1 : 3));
+        const int fq = LPP * (q & (LPP == 16 ? 1 : 3));
         double xp[RPT], xq[RPT];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-          xp[k] = wp[32 * (k >> 2) + op[k & 3]];
-          xq[k] = wq[32 * (k >> 2) + oq[k & 3]];
+          xp[k] = rp[(LPP * k) ^ fp];
+          xq[k] = rq[(LPP * k) ^ fq];
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -417,80 +417,80 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
           be = fma(xq[k], xq[k], be);
           ga = fma(xp[k], xq[k], ga);
         }
-        al = lane8_sum(al);
-        be = lane8_sum(be);
-        ga = lane8_sum(ga);
+        al = group_sum<LPP>(al);
+        be = group_sum<LPP>(be);
+        ga = group_sum<LPP>(ga);
         const bool rot = al > 0.0 && be > 0.0 && ga * ga > tol2 * al * be;
-        // rotation parameters, computed unconditionally (c = 1, s = 0 when idle)
         const double g2 = rot ? 2.0 * ga : 1.0;
-        const double zeta = rot ? (be - al) * rcp_nr(g2) : 0.0;
         // t = 1 / (|zeta| + sqrt(1 + zeta^2)); above 1e150 zeta^2 would
         // overflow and t = 1 / (2 |zeta|) is exact to rounding.  The angle must
         // not be clamped: a too large angle on a strongly graded pair
         // overshoots and the pair never settles.  An infinite zeta gives t = 0
-        // (no rotation, and the pair does not count as changed).
+        // (no rotation, and the pair does not count as changed).  t comes from
+        // the hardware reciprocal and root estimates without refinement: any
+        // t gives an exact rotation once c and s are consistent, and an angle
+        // off by the estimates' relative error leaves a coupling of that
+        // relative size, which the next sweep removes.  c = 1/sqrt(1 + t^2)
+        // is refined to full precision, so that c^2 + s^2 = 1 to rounding.
+        const double zeta = rot ? (be - al) * __builtin_amdgcn_rcp(g2) : 0.0;
         const double az = fabs(zeta);
         const double azc = fmin(az, 1e150);
         const double w = fma(azc, azc, 1.0);
-        const double den = (az < 1e150) ? azc + w * rsq_nr(w) : 2.0 * az;
-        double tt = (den < INFINITY) ? rcp_nr(den) : 0.0;
+        const double den = (az < 1e150) ? fma(w, __builtin_amdgcn_rsq(w), azc) : 2.0 * az;
+        double tt = (den < INFINITY) ? __builtin_amdgcn_rcp(den) : 0.0;
         tt = rot ? (zeta < 0.0 ? -tt : tt) : 0.0;
+        double c = 1.0, s = 0.0;
         if (tt != 0.0) {
-          const double c = rsq_nr(fma(tt, tt, 1.0));
-          const double s = c * tt;
+          c = rsq_nr(fma(tt, tt, 1.0));
+          s = c * tt;
+          double* wp = Wc + p * ld + sub;
+          double* wq = Wc + q * ld + sub;
 #pragma unroll
           for (int k = 0; k < RPT; ++k) {
-            wp[32 * (k >> 2) + op[k & 3]] = c * xp[k] - s * xq[k];
-            wq[32 * (k >> 2) + oq[k & 3]] = s * xp[k] + c * xq[k];
-          }
-          if (Vc) {
-            double* vp = Vc + p * ld + sub;
-            double* vq = Vc + q * ld + sub;
-            double yp[RPT], yq[RPT];
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-              yp[k] = vp[32 * (k >> 2) + op[k & 3]];
-              yq[k] = vq[32 * (k >> 2) + oq[k & 3]];
-            }
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-              vp[32 * (k >> 2) + op[k & 3]] = c * yp[k] - s * yq[k];
-              vq[32 * (k >> 2) + oq[k & 3]] = s * yp[k] + c * yq[k];
-            }
+            wp[(LPP * k) ^ fp] = c * xp[k] - s * xq[k];
+            wq[(LPP * k) ^ fq] = s * xp[k] + c * xq[k];
           }
           if (sub == 0) {
             changed = 1;
             if (ga * ga > 1e-18 * al * be) big = 1;
           }
         }
+        if (rotlog && sub == 0) rotlog[((size_t)sweeps * m1 + r) * P + g] = make_double2(c, s);
       }
+      kp = kp == 0 ? m1 - 1 : kp - 1;
+      kq = kq == 0 ? m1 - 1 : kq - 1;
       __syncthreads();
     }
     const int ch = changed, bg = big;
     __syncthreads();
     if (t == 0) { changed = 0; big = 0; }
     __syncthreads();
-    // Cyclic Jacobi converges quadratically: after a sweep whose largest
-    // relative coupling |ga| / sqrt(al be) was below 1e-9 the couplings left
-    // are of order 1e-18, below tol, so the rotation-free check sweep is
-    // skipped.
-    if (!ch || !bg) break;
+    ++sweeps;
+    converged = !ch || !bg;
   }
-  // singular values and ordering
-  for (int j = t; j < bp; j += nt) {
-    double s = 0.0;
-    for (int i = 0; i < b; ++i) {
-      const double w = Wc[j * ld + jac_row(i, j)];
-      s += w * w;
+  // column norms: slot g takes columns 2g and 2g + 1
+  if (active) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 2 * g + h;
+      const double* wc = Wc + col * ld + sub;
+      const int f = LPP * (col & (LPP == 16 ? 1 : 3));
+      double ss = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const double v = wc[(LPP * k) ^ f];
+        ss = fma(v, v, ss);
+      }
+      ss = group_sum<LPP>(ss);
+      if (sub == 0) {
+        const double sq = sqrt(ss);
+        if (!isfinite(sq)) bad = 1;
+        sv[col] = sq;
+      }
     }
-    s = sqrt(s);
-    if (!isfinite(s)) bad = 1;
-    sv[j] = s;
   }
   __syncthreads();
   double* so_b = so + blockIdx.x * sstride;
-  double* Uo = trans ? Yo : Xo;   // normalised columns of the working matrix
-  double* Vo = trans ? Xo : Yo;   // accumulated rotations
   for (int j = t; j < b; j += nt) {
     const double sj = sv[j];
     int rank = 0;
@@ -498,18 +498,118 @@ __global__ __launch_bounds__(512) void jacobi_svd_kernel(const double* __restric
       const double sk = sv[k];
       rank += (sk > sj || (sk == sj && k < j)) ? 1 : 0;
     }
+    rk[j] = rank;
     so_b[rank] = sj;
-    if (Uo) {
-      double* X = Uo + blockIdx.x * bstride;
+    if (rank_out) rank_out[j] = rank;
+  }
+  __syncthreads();
+  if (Uo) {
+    double* X = Uo + blockIdx.x * bstride;
+    for (int idx = t; idx < b * b; idx += nt) {
+      const int i = idx / b, j = idx - (idx / b) * b;
+      const double sj = sv[j];
       const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-      for (int i = 0; i < b; ++i) X[(long long)i * b + rank] = Wc[j * ld + jac_row(i, j)] * inv;
-    }
-    if (Vo && Vc) {
-      double* Y = Vo + blockIdx.x * bstride;
-      for (int i = 0; i < b; ++i) Y[(long long)i * b + rank] = Vc[j * ld + jac_row(i, j)];
+      X[(long long)i * b + rk[j]] = Wc[j * ld + jac_row<LPP>(i, j)] * inv;
     }
   }
-  if (t == 0 && (bad || sweep >= 60)) *err = 1;
+  if (t == 0) {
+    if (bad || !converged) *err = 1;
+    if (sweeps_out) *sweeps_out = sweeps;
+  }
+}
+
+// The accumulated rotations J of jacobi_kernel, rebuilt from its log: J
+// starts as the identity and takes the logged plane rotations in order.  The
+// rows of J evolve independently, so each wave rebuilds one row i: lane g
+// holds the row's entries in the two columns of slot g, rotates them with
+// slot g's (c, s) of the round and passes them along the ring (wave shifts by
+// one lane).  After whole sweeps the columns are back in their starting
+// slots, and entry (i, j) is written to Vo[i][rank[j]], the column order of
+// the singular values.  The log was written by one workgroup on one XCD, so
+// each of the kReplayGroups workgroups streams it through LDS in chunks of
+// kReplayChunk rounds, loading the next chunk while its waves work on the
+// current one; workgroup x rebuilds rows x, x + kReplayGroups, ... (at most
+// four rows, one wave each, so that the waves of a CU do not queue for it).
+constexpr int kReplayGroups = 32;
+constexpr int kReplayChunk = 64;
+__global__ __launch_bounds__(1024) void jacobi_replay_kernel(const double2* __restrict__ rotlog,
+                                                             const int* __restrict__ sweeps_in,
+                                                             const int* __restrict__ rank, int b,
+                                                             double* __restrict__ Vo) {
+  extern __shared__ double2 chunk[];  // 2 x kReplayChunk rounds x P slots
+  const int bp = b + (b & 1);
+  const int P = bp / 2, m1 = bp - 1;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int g = t & 63;
+  const int i = blockIdx.x + kReplayGroups * (t >> 6);  // this wave's row
+  const bool act = g < P;
+  double tv = (act && 2 * g == i) ? 1.0 : 0.0;
+  double bv = (act && 2 * g + 1 == i) ? 1.0 : 0.0;
+  const long long total = (long long)(*sweeps_in) * m1;
+  const int per = kReplayChunk * P;     // entries of one chunk
+  constexpr int kLoads = (kReplayChunk * 64 + 255) / 256;  // per thread, at >= 256 threads
+  double2 stage[kLoads];
+  // chunk 0 into buffer 0
+  for (int e = t; e < per; e += nt) chunk[e] = e < total * P ? rotlog[e] : make_double2(1.0, 0.0);
+  __syncthreads();
+  for (long long c0 = 0; c0 < total; c0 += kReplayChunk) {
+    const int buf = (int)((c0 / kReplayChunk) & 1);
+    const long long n0 = c0 + kReplayChunk;  // first round of the next chunk
+    const bool more = n0 < total;
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const long long e = (long long)t + (long long)q * nt;
+        const long long src = n0 * P + e;
+        stage[q] = (e < per && src < total * P) ? rotlog[src] : make_double2(1.0, 0.0);
+      }
+    }
+    const double2* cs = chunk + buf * per;
+    const int rounds = (int)min<long long>(kReplayChunk, total - c0);
+    for (int r = 0; r < rounds; ++r) {  // uniform over the workgroup
+      const double2 v = act ? cs[r * P + g] : make_double2(1.0, 0.0);
+      const double nt_ = v.x * tv - v.y * bv;
+      const double nb_ = v.y * tv + v.x * bv;
+      const double from_left_t = dpp64<0x138>(nt_);   // wave_shr:1, lane g <- g - 1
+      const double from_left_b = dpp64<0x138>(nb_);
+      const double from_right_b = dpp64<0x130>(nb_);  // wave_shl:1, lane g <- g + 1
+      tv = g == 0 ? nt_ : (g == 1 ? from_left_b : from_left_t);
+      // with one slot the ring is its bottom column alone
+      bv = g == P - 1 ? (P == 1 ? nb_ : nt_) : from_right_b;
+    }
+    if (more) {
+      double2* dst = chunk + (buf ^ 1) * per;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const long long e = (long long)t + (long long)q * nt;
+        if (e < per) dst[e] = stage[q];
+      }
+    }
+    __syncthreads();
+  }
+  if (act && i < b) {
+    if (2 * g < b) Vo[(long long)i * b + rank[2 * g]] = tv;
+    if (2 * g + 1 < b) Vo[(long long)i * b + rank[2 * g + 1]] = bv;
+  }
+}
+
+// One workgroup per column i: ||Y[:, i] - s_i V[:, i]||_2.
+__global__ void column_residuals_kernel(const double* __restrict__ Y, const double* __restrict__ V,
+                                        const double* __restrict__ s, int n, int ld, int kk,
+                                        double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  const double si = s[i];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const double e = fma(-si, V[(long long)r * ld + i], Y[(long long)r * ld + i]);
+    acc = fma(e, e, acc);
+  }
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) {
+    out[i] = sqrt(acc);
+    if (i == 0) out[kk] = s[0];
+  }
 }
 
 __global__ void inv_sqrt_cut_kernel(const double* s, int kk, int chi, double eps, double* w) {
@@ -674,40 +774,72 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
   CTM_HIP(hipGetLastError());
 }
 
-int jacobi_max_b(bool vectors) { return vectors ? 96 : 128; }
+int jacobi_max_b(bool) { return kJacobiMaxB; }
 
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
                 int batch, long long bstride, long long sstride, bool trans) {
-  const bool vec = (X != nullptr || Y != nullptr);
-  CTM_REQUIRE(b >= 1 && b <= jacobi_max_b(vec), "jacobi_svd: b out of range");
+  CTM_REQUIRE(b >= 1 && b <= kJacobiMaxB, "jacobi_svd: b out of range");
+  double* Uo = trans ? Y : X;  // normalised columns of the working matrix
+  double* Vo = trans ? X : Y;  // accumulated rotations
+  CTM_REQUIRE(Vo == nullptr || batch == 1, "jacobi_svd: rotations of one matrix at a time");
   const int bp = b + (b & 1);
-  int rpt = (b + 7) / 8;
-  rpt = rpt <= 4 ? 4 : (rpt <= 8 ? 8 : (rpt <= 12 ? 12 : 16));
-  const int ld = 8 * rpt;
-  const size_t lds = ((vec ? 2 : 1) * (size_t)bp * ld + bp) * sizeof(double) +
-                     (size_t)(bp - 1) * bp + 16;
+  const int P = bp / 2;
+  constexpr int LPP = 16;
+  int rpt = (b + LPP - 1) / LPP;
+  rpt += rpt & 1;  // whole pairs of 16-row blocks
+  const int ld = LPP * rpt;
+  const size_t lds = ((size_t)bp * ld + bp) * sizeof(double) + (size_t)bp * sizeof(int);
   CTM_REQUIRE(lds <= 160 * 1024, "jacobi_svd: matrix too large for LDS");
-  const int threads = std::max(64, (bp / 2) * 8);
-  CTM_REQUIRE(threads <= 512, "jacobi_svd: too many column pairs");
-#define CTM_JAC(R)                                                                            \
-  do {                                                                                        \
-    allow_lds((const void*)jacobi_svd_kernel<R>, lds);                                        \
-    hipLaunchKernelGGL(jacobi_svd_kernel<R>, dim3(batch), dim3(threads), lds, ctx.stream, B, b, \
-                       bstride, sstride, X, s, Y, err, vec ? 1 : 0, trans ? 1 : 0);          \
+  const int threads = std::max(64, (P * LPP + 63) / 64 * 64);
+  double2* rotlog = nullptr;
+  int* rank = nullptr;
+  int* sweeps = nullptr;
+  if (Vo) {
+    // one fixed-size workspace per context (its address never changes, so
+    // captured graphs stay valid): the rotation log of the largest matrix
+    // for the most sweeps, the ranks and the sweep count
+    const size_t logb = (size_t)kJacobiMaxSweeps * (kJacobiMaxB - 1) * (kJacobiMaxB / 2) *
+                        sizeof(double2);
+    const size_t need = logb + (kJacobiMaxB + 64) * sizeof(int);
+    if (ctx.jacobi_ws.bytes < need) {
+      CTM_HIP(hipStreamSynchronize(ctx.stream));
+      ctx.jacobi_ws.alloc(need);
+    }
+    rotlog = (double2*)ctx.jacobi_ws.p;
+    rank = (int*)((char*)ctx.jacobi_ws.p + logb);
+    sweeps = rank + kJacobiMaxB;
+  }
+#define CTM_JAC(R)                                                                                \
+  do {                                                                                            \
+    allow_lds((const void*)jacobi_kernel<R, LPP>, lds);                                           \
+    hipLaunchKernelGGL((jacobi_kernel<R, LPP>), dim3(batch), dim3(threads), lds, ctx.stream, B, b, \
+                       bstride, sstride, Uo, s, rotlog, rank, sweeps, err, trans ? 1 : 0);        \
   } while (0)
-  if (rpt == 4) CTM_JAC(4);
-  else if (rpt == 8) CTM_JAC(8);
-  else if (rpt == 12) CTM_JAC(12);
-  else CTM_JAC(16);
+  if (rpt == 2) CTM_JAC(2);
+  else if (rpt == 4) CTM_JAC(4);
+  else if (rpt == 6) CTM_JAC(6);
+  else CTM_JAC(8);
 #undef CTM_JAC
   CTM_HIP(hipGetLastError());
+  if (Vo) {
+    const int rows = (b + kReplayGroups - 1) / kReplayGroups;  // waves per workgroup
+    const size_t clds = 2ull * kReplayChunk * P * sizeof(double2);
+    allow_lds((const void*)jacobi_replay_kernel, clds);
+    hipLaunchKernelGGL(jacobi_replay_kernel, dim3(kReplayGroups), dim3(64 * std::max(rows, 4)), clds,
+                       ctx.stream, rotlog, sweeps, rank, b, Vo);
+    CTM_HIP(hipGetLastError());
+  }
 }
 
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
                   int* err) {
-  CTM_REQUIRE(b >= 1 && b <= 96, "chol_inverse: b out of range");
-  hipLaunchKernelGGL((chol_inv_kernel<32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol, W,
-                     dep, err);
+  CTM_REQUIRE(b >= 1 && b <= 128, "chol_inverse: b out of range");
+  if (b <= 96)
+    hipLaunchKernelGGL((chol_inv_kernel<96, 32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol,
+                       W, dep, err);
+  else
+    hipLaunchKernelGGL((chol_inv_kernel<128, 32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol,
+                       W, dep, err);
   CTM_HIP(hipGetLastError());
 }
 
@@ -718,6 +850,14 @@ void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* d
   const size_t total = (size_t)n * b;
   hipLaunchKernelGGL(refill_kernel, dim3(grid_for(total, 256, 1024)), dim3(256), 0, ctx.stream, Q,
                      ldq, n, b, dep, seed, counter_in, counter_out);
+  CTM_HIP(hipGetLastError());
+}
+
+void column_residuals(Context& ctx, const double* Y, const double* V, const double* s, int n,
+                      int ld, int kk, double* out) {
+  if (kk <= 0) return;
+  hipLaunchKernelGGL(column_residuals_kernel, dim3(kk), dim3(256), 0, ctx.stream, Y, V, s, n, ld,
+                     kk, out);
   CTM_HIP(hipGetLastError());
 }
 

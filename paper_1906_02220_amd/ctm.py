@@ -30,8 +30,6 @@ CTM_PREC_F64 = 0
 CTM_PREC_F32 = 1
 CTM_PREC_BF16X3 = 3
 CTM_PREC_BF16X4 = 4
-CTM_PREC_BF16X5 = 5
-CTM_PREC_BF16X6 = 6
 
 _STATUS_NAMES = {0: "CTM_OK", 1: "CTM_ENOTCONV", -1: "CTM_EINVAL", -2: "CTM_ENOMEM",
                  -3: "CTM_EDEVICE", -4: "CTM_ENUMERIC"}
@@ -50,7 +48,10 @@ class ctm_opts(ctypes.Structure):
                 ("svd_iters", ctypes.c_int),
                 ("svd_iters_cold", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong),
-                ("boundary", ctypes.POINTER(ctypes.c_double))]
+                ("boundary", ctypes.POINTER(ctypes.c_double)),
+                ("svd_oversample", ctypes.c_int),
+                ("svd_tol", ctypes.c_double),
+                ("move_order", ctypes.c_int * 4)]
 
 
 class ctm_grad_info(ctypes.Structure):
@@ -106,6 +107,8 @@ SIGNATURES = {
     "ctm_env_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "ctm_env_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "ctm_env_dims": (ctypes.c_int, [_P, _I, _I, _I, _I]),
+    "ctm_svd_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
+                                     ctypes.POINTER(ctypes.c_longlong), _D]),
     "ctm_grad_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.POINTER(ctm_opts), ctypes.c_int,
                                              ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
@@ -188,6 +191,8 @@ def default_opts(**kw):
     for k, v in kw.items():
         if k == "boundary":
             continue
+        if k == "move_order":
+            v = (ctypes.c_int * 4)(*[int(x) for x in v])
         setattr(o, k, v)
     return o
 
@@ -494,6 +499,14 @@ class Environment:
                                                           ctypes.byref(xi)),
                        "ctm_transfer_spectrum")
         return re + 1j * im, xi.value
+
+    def svd_stats(self):
+        """(truncated SVDs by subspace iteration, their iterations, residual
+        max_i ||M u_i - s_i v_i|| / s_1 of the last move's kept triplets)."""
+        calls, iters, res = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_double()
+        self.ctx.check(self.ctx.lib.ctm_svd_stats(self.h, ctypes.byref(calls), ctypes.byref(iters),
+                                                  ctypes.byref(res)), "ctm_svd_stats")
+        return calls.value, iters.value, res.value
 
     def corner_spectra(self):
         out = np.empty(4 * self.chi)
