@@ -35,8 +35,13 @@ def _rel(x, y):
 
 
 @pytest.mark.parametrize("D,chi,gamma,iters", [(2, 8, 0, 0), (2, 8, 1, 0), (2, 8, 2, 0),
-                                               (3, 12, 2, 12)])
+                                               (3, 12, 2, 12), (4, 16, 2, 0), (5, 20, 0, 0)])
 def test_bond_update_matches_oracle(ctx, D, chi, gamma, iters):
+    """D = 2 ... 5: normal matrices of n = D^3 = 8, 27, 64 and 125 unknowns,
+    so the one-workgroup Cholesky solve runs its trailing update over n^2
+    entries in one pass (n <= 27) and in strided passes of 1024 (n = 64,
+    125); the gated composites' cut matrices (chi d = 256, 500) go through
+    the subspace SVD."""
     say("case: FU bond update D=%d chi=%d gamma=%d" % (D, chi, gamma))
     A, B = synth.random_purification(D, 21, gamma=gamma)
     H = synth.bond_operator_real(synth.random_coefficients(22))

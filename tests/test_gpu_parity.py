@@ -98,7 +98,7 @@ def test_honeycomb_ising_closed_forms(ctx, gamma):
 
 
 def test_honeycomb_padded_gauged_subspace_path(ctx):
-    """Dense D = 4 tensors of rank 2 per bond: chi * d = 256 > 96 takes the
+    """Dense D = 4 tensors of rank 2 per bond: chi * d = 256 > 128 takes the
     subspace-iteration SVD through rank-deficient cut matrices."""
     say("case: honeycomb padded+gauged D=4 chi=16")
     K = 0.4
@@ -115,7 +115,7 @@ def test_honeycomb_padded_gauged_subspace_path(ctx):
 def test_maximum_size_padded_gauged(ctx, mode):
     """The largest supported shape: D = 7 (d = 49) and chi = 96, so the cut
     matrix is n = 4704 (49 full 96-wide FP64 tiles, 36.75 128-wide slice
-    tiles) and the subspace SVD runs at its maximum block b = chi = 96.  The
+    tiles) and the subspace SVD runs with b = chi + 24 = 120 columns.  The
     honeycomb Ising state padded from D = 2 and gauged on every bond is the
     same state, so kappa and <sigma sigma> still equal Houtappel's closed
     forms."""
@@ -276,3 +276,37 @@ def test_error_paths(ctx):
     with pytest.raises(ctm.CtmError) as ei:
         env2.sweep(2, 0.0)
     assert ei.value.code == ctm.CTM_ENUMERIC
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2, 3), (3, 1, 0, 2)])
+def test_move_order_option(ctx, order):
+    """ctm_opts.move_order: a sweep of moves in a user order, against the
+    oracle's left moves of the frames rotated by the same directions.
+    D = 3, chi = 20 (n = 180: subspace SVD), 8 sweeps."""
+    say("case: move order %s, D=3 chi=20" % (order,))
+    D, chi, sweeps = 3, 20, 8
+    A, B = synth.random_purification(D, 4, gamma=1)
+    env = ctm.Environment.from_purification(ctx, A, B, 1, chi, move_order=order)
+    env.sweep(sweeps, 0.0)
+    K = O.composite(A, B, 1)
+    a = O.double_layer(K)
+    arot = [O.rotate(a, k) for k in range(4)]
+    oenv = O.init_env(D * D, chi, O.boundary_vector_double_layer(D))
+    for _ in range(sweeps):
+        for k in order:
+            O.left_move(oenv, arot, k, chi)
+    H = synth.bond_operator_real(synth.random_coefficients(6))
+    assert abs(env.norm() / O.kappa(oenv, a) - 1.0) < 1e-10
+    assert abs(env.expect(H) - O.expect(oenv, a, O.double_layer(K, O.full_operator(H, 4)))) < 1e-10
+    # the default order is a different iteration: the environments differ
+    dflt = ctm.Environment.from_purification(ctx, A, B, 1, chi)
+    dflt.sweep(2, 0.0)
+    e2 = ctm.Environment.from_purification(ctx, A, B, 1, chi, move_order=order)
+    e2.sweep(2, 0.0)
+    assert dflt.norm() != e2.norm()
+    o = ctm.default_opts()
+    o.move_order = (ctypes.c_int * 4)(0, 1, 1, 3)
+    h = ctm._P()
+    rc = ctm.ctm_env_init_purification(ctx.h, A.ctypes.data_as(ctm._D), B.ctypes.data_as(ctm._D),
+                                       D, D, 1, chi, ctypes.byref(o), ctypes.byref(h))
+    assert rc == ctm.CTM_EINVAL and b"permutation" in ctm.ctm_last_error(ctx.h)
