@@ -233,6 +233,24 @@ int ctm_bond_metric(ctm_env* env, double* E, size_t len);
  * caller passes its real part. */
 int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value);
 
+/* ctm_expect for callers that cannot allocate device memory (serving loops
+ * that evaluate many operators on one converged environment, code that must
+ * not call hipMalloc): the same <O>, computed without any allocation.  The
+ * per-call buffers (the D^4 x 16 partial contraction, rho, the operator,
+ * reduction and split-K partial sums) live in a fixed device array of 8 MiB
+ * that the library holds on every GPU it runs on until the process ends.
+ * op, op_dim, value: as for ctm_expect (op is host memory, read during the
+ * call; value is written before return).
+ * Requirements: the environment's ring must be current, i.e. ctm_norm,
+ * ctm_expect, ctm_log_z or ctm_bond_metric has run once since the last sweep
+ * or move (contracting the ring needs workspace this call does not
+ * allocate); D <= 8 (16 D^4 + 1344 doubles must fit the array).  Either
+ * failure returns CTM_EINVAL and runs nothing.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind (nothing in it needs to
+ * start at zero): calls that overlap on one GPU, from several threads or
+ * streams, race. */
+int ctm_expect_noalloc(ctm_env* env, const double* op, int op_dim, double* value);
+
 /* <E, a_imp> / <E, a> for an impurity site tensor a_imp[u][l][d][r] (d^4
  * doubles, host), any environment. */
 int ctm_expect_tensor(ctm_env* env, const double* a_imp, double* value);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <fstream>
 #include <memory>
 #include <string>
@@ -74,6 +75,33 @@ void Context::resolve_timing() {
 }
 
 }  // namespace ctm
+
+// Fixed device scratch of ctm_expect_noalloc: every GPU the library runs on
+// holds its own copy of this array until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device when the first context on that device is
+// created, with that device current.
+static constexpr size_t kNoAllocScratchDoubles = size_t(1) << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch (the device must be current).
+static double* scratch_address(int device) {
+  CTM_REQUIRE(device >= 0 && device < kMaxDevices, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    double* ptr = nullptr;
+    CTM_HIP(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    CTM_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
 
 namespace {
 
@@ -184,6 +212,7 @@ int ctm_context_create(int device, ctm_context** out) {
     ctx->c.num_cus = prop.multiProcessorCount;
     CTM_HIP(hipStreamCreateWithFlags(&ctx->c.own_stream, hipStreamNonBlocking));
     ctx->c.stream = ctx->c.own_stream;
+    (void)scratch_address(device);  // set-up of the no-allocation entry point
   });
   if (rc != CTM_OK) {
     delete ctx;
@@ -749,6 +778,16 @@ int ctm_expect(ctm_env* env, const double* op, int op_dim, double* value) {
   return guarded_c(env->owner_c, [&] {
     CTM_REQUIRE(op && value, "null argument");
     *value = env->e->expect_op(op, op_dim);
+  });
+}
+
+int ctm_expect_noalloc(ctm_env* env, const double* op, int op_dim, double* value) {
+  if (!env) return CTM_EINVAL;
+  return guarded_c(env->owner_c, [&] {
+    CTM_REQUIRE(op && value, "null argument");
+    CTM_HIP(hipSetDevice(env->owner_c->device));
+    double* ptr = scratch_address(env->owner_c->device);
+    *value = env->e->expect_op_fixed(op, op_dim, ptr, kNoAllocScratchDoubles);
   });
 }
 

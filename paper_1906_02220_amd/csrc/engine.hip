@@ -720,16 +720,16 @@ void Env::ring_ket_bra_dev(double* out) {
   permute(ctx, E.d(), out, 8, dd, pp);
 }
 
-// <O> from the 16 x 16 matrix rho[q][p] = sum K[q,ket] E8[ket,bra] K[p,bra]:
-// <O> = sum_pq O[p][q] rho[q][p] / tr(rho).
-double Env::expect_op(const double* op, int op_dim) {
-  CTM_REQUIRE(D > 0, "ctm_expect needs a purification environment");
+// The operator on the composite's physical index p = (sA, aA, sB, aB): op
+// itself (op_dim 16) or op on (sA, sB) times the identity on the ancillas
+// (op_dim 4); O and I16 are 16 x 16 row-major.
+static void composite_operator(const double* op, int op_dim, double* O, double* I16) {
   CTM_REQUIRE(op_dim == 4 || op_dim == 16, "op_dim must be 4 or 16");
-  std::vector<double> O(256, 0.0), I16(256, 0.0);
+  for (int i = 0; i < 256; ++i) { O[i] = 0.0; I16[i] = 0.0; }
   if (op_dim == 16) {
-    std::memcpy(O.data(), op, 256 * sizeof(double));
+    std::memcpy(O, op, 256 * sizeof(double));
   } else {
-    // p = (sA, aA, sB, aB): O[(sA aA sB aB),(sA' aA' sB' aB')] = op[(sA sB),(sA' sB')] d_aA d_aB
+    // O[(sA aA sB aB),(sA' aA' sB' aB')] = op[(sA sB),(sA' sB')] d_aA d_aB
     for (int sA = 0; sA < 2; ++sA) for (int aA = 0; aA < 2; ++aA)
     for (int sB = 0; sB < 2; ++sB) for (int aB = 0; aB < 2; ++aB)
     for (int tA = 0; tA < 2; ++tA) for (int tB = 0; tB < 2; ++tB) {
@@ -739,26 +739,79 @@ double Env::expect_op(const double* op, int op_dim) {
     }
   }
   for (int i = 0; i < 16; ++i) I16[i * 16 + i] = 1.0;
-  ring();
+}
+
+// <O> = sum_pq O[p][q] rho[q][p] / tr(rho) from the 16 x 16 matrix
+// rho[q][p] = sum K[q,ket] E8[ket,bra] K[p,bra], with F (D^4 x 16), rhoT,
+// the operator and the identity in the given device buffers.
+double Env::expect_from_ring(const double* O, const double* I16, double* F, double* rhoT,
+                             double* dO, double* dI) {
   const long long dd[8] = {D, D, D, D, D, D, D, D};
   const int pp[8] = {0, 2, 4, 6, 1, 3, 5, 7};
   permute(ctx, E.d(), E8.d(), 8, dd, pp);
   const int D4 = D * D * D * D;
-  DevBuf F((size_t)D4 * 16 * sizeof(double)), rhoT(256 * sizeof(double));
   // F[ket][p] = sum_bra E8[ket][bra] K[p][bra];  rho^T[p][q] = sum_ket F[ket][p] K[q][ket]
   gemm_f64(ctx, D4, 16, D4, 1.0, rowmajor(E8.d(), D4), colmajor(Kc.d(), D4), 0.0,
-           out_rowmajor(F.d(), 16));
-  gemm_f64(ctx, 16, 16, D4, 1.0, colmajor(F.d(), 16), colmajor(Kc.d(), D4), 0.0,
-           out_rowmajor(rhoT.d(), 16));  // rhoT[p][q] = rho[q][p]
-  DevBuf dO(256 * sizeof(double)), dI(256 * sizeof(double));
-  CTM_HIP(hipMemcpyAsync(dO.p, O.data(), 256 * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  CTM_HIP(hipMemcpyAsync(dI.p, I16.data(), 256 * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  dot(ctx, dO.d(), rhoT.d(), 256, scal.d() + 6);
-  dot(ctx, dI.d(), rhoT.d(), 256, scal.d() + 7);
-  double r[2];
-  CTM_HIP(hipMemcpyAsync(r, scal.d() + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+           out_rowmajor(F, 16));
+  gemm_f64(ctx, 16, 16, D4, 1.0, colmajor(F, 16), colmajor(Kc.d(), D4), 0.0,
+           out_rowmajor(rhoT, 16));  // rhoT[p][q] = rho[q][p]
+  CTM_HIP(hipMemcpyAsync(dO, O, 256 * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  CTM_HIP(hipMemcpyAsync(dI, I16, 256 * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  dot(ctx, dO, rhoT, 256, scal.d() + 6);
+  dot(ctx, dI, rhoT, 256, scal.d() + 7);
+  CTM_HIP(hipMemcpyAsync(hres, scal.d() + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   CTM_HIP(hipStreamSynchronize(ctx.stream));
-  return r[0] / r[1];
+  return hres[0] / hres[1];
+}
+
+double Env::expect_op(const double* op, int op_dim) {
+  CTM_REQUIRE(D > 0, "ctm_expect needs a purification environment");
+  double O[256], I16[256];
+  composite_operator(op, op_dim, O, I16);
+  ring();
+  const int D4 = D * D * D * D;
+  DevBuf F((size_t)D4 * 16 * sizeof(double)), rhoT(256 * sizeof(double));
+  DevBuf dO(256 * sizeof(double)), dI(256 * sizeof(double));
+  return expect_from_ring(O, I16, F.d(), rhoT.d(), dO.d(), dI.d());
+}
+
+size_t Env::expect_scratch_doubles() const {
+  const size_t D4 = (size_t)D * D * D * D;
+  return 16 * D4 + 3 * 256 + kRedScratchDoubles;
+}
+
+double Env::expect_op_fixed(const double* op, int op_dim, double* scratch, size_t scratch_doubles) {
+  CTM_REQUIRE(D > 0, "ctm_expect_noalloc needs a purification environment");
+  CTM_REQUIRE(e_valid, "ctm_expect_noalloc: the ring of this environment is not current (run "
+                       "ctm_norm, ctm_expect or ctm_bond_metric once after the last sweep)");
+  double O[256], I16[256];
+  composite_operator(op, op_dim, O, I16);
+  const size_t D4 = (size_t)D * D * D * D;
+  const size_t fixed = expect_scratch_doubles();
+  CTM_REQUIRE(fixed < scratch_doubles, "ctm_expect_noalloc: D is beyond the fixed scratch");
+  double* F = scratch;
+  double* rhoT = F + 16 * D4;
+  double* dO = rhoT + 256;
+  double* dI = dO + 256;
+  double* red = dI + 256;
+  // the rest takes the split-K partial sums of the two products
+  struct Fixed {
+    Context& c;
+    bool timing;
+    Fixed(Context& cc, double* red, double* part, size_t bytes) : c(cc), timing(cc.timing) {
+      c.fixed_red = red;
+      c.fixed_splitk = part;
+      c.fixed_splitk_bytes = bytes;
+      c.timing = false;  // per-launch events are not created either
+    }
+    ~Fixed() {
+      c.fixed_red = nullptr;
+      c.fixed_splitk = nullptr;
+      c.fixed_splitk_bytes = 0;
+      c.timing = timing;
+    }
+  } guard(ctx, red, scratch + fixed, (scratch_doubles - fixed) * sizeof(double));
+  return expect_from_ring(O, I16, F, rhoT, dO, dI);
 }
 
 double Env::expect_tensor(const double* a_imp) {

@@ -90,6 +90,11 @@ class Env {
   void ring_ket_bra_dev(double* out);
   const double* composite_dev() const { return Kc.d(); }  // 16 x D^4
   double expect_op(const double* op, int op_dim);
+  // expect_op on the current ring with every device buffer taken from
+  // `scratch` (scratch_doubles doubles of device memory): nothing is
+  // allocated.  Refused when the ring is not current or D is too large.
+  double expect_op_fixed(const double* op, int op_dim, double* scratch, size_t scratch_doubles);
+  size_t expect_scratch_doubles() const;
   double expect_tensor(const double* a_imp_host);
   void corner_spectra(double* host_out, size_t len);
   void get(double* C, double* T, double* logs);
@@ -122,6 +127,8 @@ class Env {
   double svd_residual(const double* Mt);
   void orth(double* Z, double* Q, int passes);
   void ring();
+  double expect_from_ring(const double* O, const double* I16, double* F, double* rhoT, double* dO,
+                          double* dI);
   void reset_spectra();
   void check_flags(const char* where);
   const double* Cp(int i) const { return Call.d() + (size_t)(i & 3) * chi * chi; }

@@ -476,6 +476,22 @@ static bool rr_vec(const View& X) {
 // K chunks of a dgemm_rr product: three workgroups fit on a CU; K is split
 // when the tiles fill less than one pass and every chunk keeps at least 32 K
 // tiles.
+// Device memory for `need` bytes of partial products: the caller's fixed
+// scratch when the context has one (refused if too small), otherwise the
+// context's workspace, grown when needed.
+static double* splitk_space(Context& ctx, size_t need) {
+  if (ctx.fixed_splitk) {
+    CTM_REQUIRE(need <= ctx.fixed_splitk_bytes,
+                "the product's partial sums do not fit the fixed scratch");
+    return ctx.fixed_splitk;
+  }
+  if (ctx.splitk_ws.bytes < need) {
+    CTM_HIP(hipStreamSynchronize(ctx.stream));
+    ctx.splitk_ws.alloc(need);
+  }
+  return ctx.splitk_ws.d();
+}
+
 static int rr_ksplit(const Context& ctx, int M, int N, int K, int batch, int& kchunk) {
   constexpr int BM = 96, BN = 96, BK = 16;
   const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
@@ -532,14 +548,7 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
     int ksplit = rr_ksplit(ctx, M, N, K, batch, kchunk);
     const bool direct = rr_direct(M, N, alpha, beta, C);
     double* W = nullptr;
-    if (ksplit > 1 || !direct) {
-      const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
-      if (ctx.splitk_ws.bytes < need) {
-        CTM_HIP(hipStreamSynchronize(ctx.stream));
-        ctx.splitk_ws.alloc(need);
-      }
-      W = ctx.splitk_ws.d();
-    }
+    if (ksplit > 1 || !direct) W = splitk_space(ctx, (size_t)ksplit * batch * M * N * sizeof(double));
     const int lda = (int)A.rs, ldb = (int)B.rs, ldc = (int)C.rs;
     const bool va = rr_vec(A), vb = rr_vec(B);
     if (ksplit == 1 && direct && ctx.autotune && va && vb) {
@@ -625,12 +634,7 @@ void gemm_f64(Context& ctx, int M, int N, int K, double alpha, View A, View B, d
     kchunk = (K + ksplit - 1) / ksplit;
     kchunk = (kchunk + BK - 1) / BK * BK;
     ksplit = (K + kchunk - 1) / kchunk;
-    const size_t need = (size_t)ksplit * batch * M * N * sizeof(double);
-    if (ctx.splitk_ws.bytes < need) {
-      CTM_HIP(hipStreamSynchronize(ctx.stream));
-      ctx.splitk_ws.alloc(need);
-    }
-    W = ctx.splitk_ws.d();
+    W = splitk_space(ctx, (size_t)ksplit * batch * M * N * sizeof(double));
   }
   const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch * ksplit);
   CTM_REQUIRE(grid.y <= 65535 && grid.z <= 65535, "gemm: grid too large");

@@ -91,6 +91,12 @@ struct Context {
   DevBuf mixed_ws;      // operand slices and scales of the reduced-precision GEMMs
   DevBuf scratch_small; // reductions and flags
   DevBuf jacobi_ws;     // rotation log, ranks and sweep count of the Jacobi SVD
+  // When set, the split-K partials of gemm_f64 and the reduction partials go
+  // to this caller-provided device memory instead of the workspaces above,
+  // and a product whose partials do not fit is refused: nothing is allocated.
+  double* fixed_splitk = nullptr;
+  size_t fixed_splitk_bytes = 0;
+  double* fixed_red = nullptr;  // at least kRedScratchDoubles
   Context() = default;
   Context(const Context&) = delete;
   Context& operator=(const Context&) = delete;
@@ -237,6 +243,9 @@ void permute(Context& ctx, const double* in, double* out, int rank, const long l
              const int* perm);
 
 // ---------------------------------------------------------------- small kernels
+
+// Doubles of reduction scratch the two-stage reductions use.
+constexpr size_t kRedScratchDoubles = 512 + 64;
 
 void fill_zero(Context& ctx, double* p, size_t n);
 void fill_zero_int(Context& ctx, int* p, size_t n);

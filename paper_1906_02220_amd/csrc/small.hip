@@ -714,6 +714,8 @@ inline int grid_for(size_t n, int block = 256, int cap = 4096) {
 }
 
 double* red_scratch(Context& ctx) {
+  static_assert(kRedBlocks + 64 <= kRedScratchDoubles, "reduction scratch size");
+  if (ctx.fixed_red) return ctx.fixed_red;
   if (ctx.scratch_small.bytes < (kRedBlocks + 64) * sizeof(double)) {
     CTM_HIP(hipStreamSynchronize(ctx.stream));
     ctx.scratch_small.alloc((kRedBlocks + 64) * sizeof(double));

@@ -100,6 +100,7 @@ SIGNATURES = {
     "ctm_log_z": (ctypes.c_int, [_P, _D, _D]),
     "ctm_bond_metric": (ctypes.c_int, [_P, _D, ctypes.c_size_t]),
     "ctm_expect": (ctypes.c_int, [_P, _D, ctypes.c_int, _D]),
+    "ctm_expect_noalloc": (ctypes.c_int, [_P, _D, ctypes.c_int, _D]),
     "ctm_expect_tensor": (ctypes.c_int, [_P, _D, _D]),
     "ctm_corner_spectra": (ctypes.c_int, [_P, _D, ctypes.c_size_t]),
     "ctm_env_get": (ctypes.c_int, [_P, _D, _D, _D]),
