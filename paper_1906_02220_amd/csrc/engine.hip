@@ -289,6 +289,10 @@ void Env::svd_top(const double* MtP, int k) {
     orth(Z0.d(), Om.d(), 2);
     iters = opt.svd_iters_cold;
   }
+  // Every right basis gets two CholeskyQR passes: with one pass on the
+  // intermediate ones the orthogonality error of each pass accumulates over
+  // the iterations (12 iterations from the boundary start at D = 6, chi = 72
+  // then left kappa 8e-9 from the full SVD's instead of 1e-10).
   for (int it = 0; it < iters; ++it) subspace_iteration(MtP);
   rayleigh_ritz(MtP);
   ++svd_calls;

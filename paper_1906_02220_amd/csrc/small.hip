@@ -223,10 +223,13 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
   // The NB steps are unrolled so that k, and with it the register row
   // k / TG that holds row k and the blocks the step can touch, are
   // compile-time constants: no select chains, and register blocks that lie
-  // entirely before the pivot are skipped.  Row k is broadcast through a
-  // double-buffered LDS row, so one barrier per step suffices (a buffer is
-  // rewritten two steps later, after every reader has passed the barrier in
-  // between).
+  // entirely before the pivot are skipped (a rolled loop with select chains
+  // ran at 78 against 48 us for b = 96).  Only the upper triangle of S is
+  // ever read (row k, right of the pivot), so blocks below the diagonal
+  // (r > c) are not updated; X is lower triangular, so blocks above it
+  // (c > r) stay zero.  Row k is broadcast through a double-buffered LDS row,
+  // so one barrier per step suffices (a buffer is rewritten two steps later,
+  // after every reader has passed the barrier in between).
 #pragma unroll NB
   for (int k = 0; k < NB; ++k) {
     if (k >= b) continue;                                     // uniform: b is a kernel argument
@@ -256,11 +259,13 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
       if (TG * r + TG - 1 < k) continue;                     // rows all before the pivot
       const int i = ti + TG * r;
       const double mi = (i > k) ? rowk[buf][i] * ipiv : 0.0;
-      const double sc = (i == k) ? ir : 1.0;
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
-        if (TG * c + TG - 1 > k) S[r][c] = fma(-mi, sr[c], S[r][c]);
-        if (TG * c <= k) X[r][c] = fma(-mi, xr[c], X[r][c]) * sc;
+        if (TG * c + TG - 1 > k && c >= r) S[r][c] = fma(-mi, sr[c], S[r][c]);
+        if (TG * c <= k && c <= r) {
+          const double v = fma(-mi, xr[c], X[r][c]);
+          X[r][c] = (r == rk) ? (i == k ? v * ir : v) : v;
+        }
       }
     }
     if (t == 0) depl[k] = dk ? 1 : 0;
@@ -566,16 +571,29 @@ __global__ __launch_bounds__(1024) void jacobi_replay_kernel(const double2* __re
     }
     const double2* cs = chunk + buf * per;
     const int rounds = (int)min<long long>(kReplayChunk, total - c0);
-    for (int r = 0; r < rounds; ++r) {  // uniform over the workgroup
-      const double2 v = act ? cs[r * P + g] : make_double2(1.0, 0.0);
-      const double nt_ = v.x * tv - v.y * bv;
-      const double nb_ = v.y * tv + v.x * bv;
-      const double from_left_t = dpp64<0x138>(nt_);   // wave_shr:1, lane g <- g - 1
-      const double from_left_b = dpp64<0x138>(nb_);
-      const double from_right_b = dpp64<0x130>(nb_);  // wave_shl:1, lane g <- g + 1
-      tv = g == 0 ? nt_ : (g == 1 ? from_left_b : from_left_t);
-      // with one slot the ring is its bottom column alone
-      bv = g == P - 1 ? (P == 1 ? nb_ : nt_) : from_right_b;
+    // groups of 8 rounds, their (c, s) read from LDS before the first of
+    // them is applied, so that the LDS latency stays off the chain of
+    // dependent rotations (rounds past the chunk's end are the identity)
+    for (int r0 = 0; r0 < rounds; r0 += 8) {  // uniform over the workgroup
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (act && r0 + u < rounds) ? cs[(r0 + u) * P + g] : make_double2(1.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double nt_ = v[u].x * tv - v[u].y * bv;
+        const double nb_ = v[u].y * tv + v[u].x * bv;
+        const double from_left_t = dpp64<0x138>(nt_);   // wave_shr:1, lane g <- g - 1
+        const double from_left_b = dpp64<0x138>(nb_);
+        const double from_right_b = dpp64<0x130>(nb_);  // wave_shl:1, lane g <- g + 1
+        const double t1 = g == 0 ? nt_ : (g == 1 ? from_left_b : from_left_t);
+        // with one slot the ring is its bottom column alone
+        const double b1 = g == P - 1 ? (P == 1 ? nb_ : nt_) : from_right_b;
+        // a round past the chunk's end does not move the ring either
+        const bool live = r0 + u < rounds;
+        tv = live ? t1 : tv;
+        bv = live ? b1 : bv;
+      }
     }
     if (more) {
       double2* dst = chunk + (buf ^ 1) * per;

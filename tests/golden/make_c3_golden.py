@@ -9,9 +9,15 @@ Runs the FP64 oracle only (oracle/ctmrg.py): the purification of seed 1234
 bond (Sec. III, Fig. 4(b)), environment from the boundary start, two full
 sweeps L, R, U, D (Fig. 4(c)), then the observables of the fused bond
 (Sec. III, last paragraph): kappa, <H_bond> for the seeded real bond
-operator, the bond metric E (stored as its Frobenius norm and three
-projections on seeded random tensors), the corner spectra, and for every
-move the gap s_chi / s_(chi+1) of the cut spectrum.
+operator, the bond metric E (its Frobenius norm, three projections on
+seeded random tensors, its largest |entry| and the entries at 65536 sampled
+flat indices), the corner spectra, and for every move the gap
+s_chi / s_(chi+1) of the cut spectrum.
+
+Sampled entries: flat index i_k = (7919 k + 13) mod D^8 of the bond metric
+in its layout [u_k][l_k][d_k][r_k][u_b][l_b][d_b][r_b], k = 0 .. 65535
+(7919 is prime and D^8 = 2^8 3^8, so the indices are distinct and spread
+over every leg).
 """
 import json
 import os
@@ -29,6 +35,13 @@ from paper_1906_02220_amd import synth  # noqa: E402
 
 D, CHI, SEED, GAMMA = 6, 72, 1234, 2
 PROJ_SEEDS = (101, 102, 103)
+N_SAMPLES, SAMPLE_STRIDE, SAMPLE_OFFSET = 65536, 7919, 13
+
+
+def sample_indices(size):
+    """Flat indices of the stored bond-metric entries."""
+    k = np.arange(N_SAMPLES, dtype=np.int64)
+    return (SAMPLE_STRIDE * k + SAMPLE_OFFSET) % size
 
 
 def out_path(sweeps):
@@ -71,6 +84,10 @@ def main(SWEEPS):
         "bond_metric_norm": float(np.linalg.norm(E8)),
         "bond_metric_projections": projections(E8),
         "projection_seeds": list(PROJ_SEEDS),
+        "bond_metric_max_abs": float(np.abs(E8).max()),
+        "bond_metric_sample": {"count": N_SAMPLES, "stride": SAMPLE_STRIDE,
+                               "offset": SAMPLE_OFFSET,
+                               "values": [float(v) for v in E8.reshape(-1)[sample_indices(E8.size)]]},
         "corner_spectra": spectra.tolist(),
         "cut_gap_per_move": gaps,
         "cut_margin_decades_per_move": cut_margin,
@@ -78,7 +95,7 @@ def main(SWEEPS):
     }
     out = out_path(SWEEPS)
     with open(out, "w") as f:
-        json.dump(res, f, indent=1)
+        json.dump(res, f)
     print("wrote %s (kappa %.15g, <H> %.15g, min gap %.6f, %.0f s)" % (
         out, kap, e_h, min(gaps), res["oracle_seconds"]))
 
