@@ -310,3 +310,23 @@ def test_move_order_option(ctx, order):
     rc = ctm.ctm_env_init_purification(ctx.h, A.ctypes.data_as(ctm._D), B.ctypes.data_as(ctm._D),
                                        D, D, 1, chi, ctypes.byref(o), ctypes.byref(h))
     assert rc == ctm.CTM_EINVAL and b"permutation" in ctm.ctm_last_error(ctx.h)
+
+
+def test_fixed_sweep_count_matches_single_sweeps(ctx):
+    """A fixed number of sweeps in one call takes the corner spectra only
+    after its last two sweeps; the environment and the returned delta are
+    those of the same number of single-sweep calls, bit for bit."""
+    say("case: sweep(5) against 5 x sweep(1), D=3 chi=20")
+    A, B = synth.random_purification(3, 4)
+    e1 = ctm.Environment.from_purification(ctx, A, B, 2, 20)
+    e2 = ctm.Environment.from_purification(ctx, A, B, 2, 20)
+    rc, done, d1 = e1.sweep(5, 0.0)
+    assert rc == ctm.CTM_OK and done == 5
+    for _ in range(5):
+        _, _, d2 = e2.sweep(1, 0.0)
+    assert d1 == d2
+    assert e1.norm() == e2.norm()
+    assert np.array_equal(e1.corner_spectra(), e2.corner_spectra())
+    C1, T1, L1 = e1.get()
+    C2, T2, L2 = e2.get()
+    assert np.array_equal(C1, C2) and np.array_equal(T1, T2) and np.array_equal(L1, L2)
