@@ -671,8 +671,17 @@ __global__ void fix_signs_kernel(double* X, int ldx, double* Y, int ldy, int n) 
     }
     __syncthreads();
   }
-  const int imax = si[0];
-  const bool flip = (imax < n) && X[(long long)imax * ldx + j] < 0.0;
+  // One thread reads the sign of the pivot entry and shares it: the column
+  // is flipped in place, so a wave reading X[imax][j] itself could see the
+  // entry already flipped by the wave that owns row imax and leave its own
+  // rows as they were.
+  __shared__ int flip_s;
+  if (t == 0) {
+    const int imax = si[0];
+    flip_s = (imax < n) && X[(long long)imax * ldx + j] < 0.0;
+  }
+  __syncthreads();
+  const bool flip = flip_s != 0;
   if (flip) {
     for (int i = t; i < n; i += blockDim.x) {
       X[(long long)i * ldx + j] = -X[(long long)i * ldx + j];

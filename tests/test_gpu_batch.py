@@ -92,6 +92,43 @@ def test_sweep_batch_matches_sequential():
     assert abs(batch[1].norm() / O.kappa(oenv, a) - 1.0) < 1e-10
 
 
+@pytest.mark.parametrize("prec", [ctm.CTM_PREC_F32, ctm.CTM_PREC_F64])
+def test_many_concurrent_members_match_plain_sweeps(prec):
+    """24 purifications with (D, chi) uniform on {4,5,6} x {32,48,72}
+    (seed 777), each on its own context so that their kernels share the CUs,
+    against the same members swept alone: bit for bit.  This is the setting
+    in which an unsynchronised read of the sign pivot in the singular-vector
+    sign fix (a wave could read the pivot after another wave had already
+    flipped it, and leave its own rows unflipped) once gave one member a
+    kappa off by 5e-6."""
+    say("case: 24 concurrent members, 3 sweeps, precision %d" % prec)
+    rng = np.random.default_rng(777)
+    cfg = list(zip(rng.choice([4, 5, 6], size=24).tolist(), rng.choice([32, 48, 72], size=24).tolist()))
+    ins = [synth.random_purification(D, 778 + i, dtype=np.float32) for i, (D, _) in enumerate(cfg)]
+    ctxs = [ctm.Context(0) for _ in cfg]
+    batch = [ctm.Environment.from_purification(c, A, B, 2, chi, precision=prec)
+             for c, (D, chi), (A, B) in zip(ctxs, cfg, ins)]
+    rc, done, delta = ctm.sweep_batch(batch, 3, 0.0)
+    assert rc == ctm.CTM_OK
+    kb = [e.norm() for e in batch]
+    for e in batch:
+        e.close()
+    for c in ctxs:
+        c.close()
+    cs = ctm.Context(0)
+    bad = []
+    for i, ((D, chi), (A, B)) in enumerate(zip(cfg, ins)):
+        es = ctm.Environment.from_purification(cs, A, B, 2, chi, precision=prec)
+        _, _, dels = es.sweep(3)
+        if not (dels == delta[i] and es.norm() == kb[i]):
+            bad.append((i, D, chi, dels, delta[i], es.norm(), kb[i]))
+        es.close()
+    cs.close()
+    for b in bad:
+        say("  member %d D=%d chi=%d: delta %.17g vs %.17g, kappa %.17g vs %.17g" % b)
+    assert not bad
+
+
 def test_sweep_batch_tolerance_and_sharing_a_context():
     """With tol > 0 each environment stops on its own; environments may share
     a context (they then run in turn on its stream)."""
