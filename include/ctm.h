@@ -282,6 +282,23 @@ int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps);
  * waits for the device.  Any pointer may be NULL. */
 int ctm_svd_stats(ctm_env* env, long long* calls, long long* iterations, double* last_residual);
 
+/* Debugging aid, process-wide: on != 0 fills every device buffer the library
+ * allocates from now on (environments, context workspaces, gradient tapes)
+ * with all-ones bytes, a NaN as a double and -1 as an int, and places it
+ * between two 64 KiB guard bands of a fixed pattern, so that a kernel reading
+ * memory the library never wrote shows up in the results and one writing
+ * past either end of a buffer is caught when the buffer is freed (the bands
+ * are checked then, after waiting for the device; each damaged band is
+ * counted and reported on stderr).  on = 0 stops it for later allocations.
+ * *previous (may be NULL) gets the old state.  The environment variable
+ * CTM_POISON_ALLOC (set and not "0") turns it on at load.  Slows every
+ * allocation and free; results do not change.  Always CTM_OK. */
+int ctm_debug_poison_allocations(int on, int* previous);
+
+/* Number of damaged guard bands found so far (see above); CTM_EINVAL if
+ * count is NULL. */
+int ctm_debug_guard_violations(long long* count);
+
 /* Statistics of the last gradient call. */
 typedef struct ctm_grad_info {
   int moves;                 /* absorption moves differentiated */

@@ -875,6 +875,18 @@ int ctm_svd_stats(ctm_env* env, long long* calls, long long* iterations, double*
   });
 }
 
+int ctm_debug_poison_allocations(int on, int* previous) {
+  const int old = ctm::poison_allocations().exchange(on ? 1 : 0);
+  if (previous) *previous = old;
+  return CTM_OK;
+}
+
+int ctm_debug_guard_violations(long long* count) {
+  if (!count) return CTM_EINVAL;
+  *count = ctm::guard_violations();
+  return CTM_OK;
+}
+
 int ctm_env_dims(const ctm_env* env, int* chi, int* d, int* D, int* sweeps) {
   if (!env) return CTM_EINVAL;
   if (chi) *chi = env->e->chi;

@@ -3,7 +3,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <cstdlib>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -31,34 +33,67 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::ctm::Error(-1, msg);                                      \
   } while (0)
 
+// Debugging aid: while set, every device buffer the library allocates is
+// filled with all-ones bytes (a NaN as a double, -1 as an int) before use, so
+// that a kernel reading memory the library never wrote gives NaN or garbage
+// instead of whatever the allocator handed back (often zeros in a fresh
+// process, earlier results in a long-running one), and sits between two
+// guard bands of kGuardBytes with a fixed byte pattern that release() checks,
+// so that a kernel writing past either end of a buffer is reported.  Starts
+// from the environment variable CTM_POISON_ALLOC (set and not "0": on).
+std::atomic<int>& poison_allocations();
+constexpr size_t kGuardBytes = 64 * 1024;
+// hipMalloc of nbytes between guard bands (poisoned) or plain; returns the
+// user pointer, or nullptr on failure
+void* debug_malloc(size_t nbytes, bool guarded);
+// frees a debug_malloc pointer; a guarded one has its bands checked first
+// (waiting for the device) and a damaged band counted and reported on stderr
+void debug_free(void* p, size_t nbytes, bool guarded);
+// damaged guard bands found so far
+long long guard_violations();
+
 // Device buffer of doubles (or raw bytes) owned by the library.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool guarded = false;  // allocated between guard bands (poisoning on)
   DevBuf() = default;
   explicit DevBuf(size_t nbytes) { alloc(nbytes); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), guarded(o.guarded) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      guarded = o.guarded;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t nbytes) {
     release();
     if (nbytes == 0) return;
-    if (hipMalloc(&p, nbytes) != hipSuccess) {
-      p = nullptr;
+    const bool g = poison_allocations().load(std::memory_order_relaxed) != 0;
+    p = debug_malloc(nbytes, g);
+    if (!p) {
       (void)hipGetLastError();
       throw Error(-2, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
     }
     bytes = nbytes;
+    guarded = g;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) debug_free(p, bytes, guarded);
     p = nullptr;
     bytes = 0;
+    guarded = false;
   }
   double* d() const { return static_cast<double*>(p); }
   float* f() const { return static_cast<float*>(p); }

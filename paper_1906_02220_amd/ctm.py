@@ -110,6 +110,8 @@ SIGNATURES = {
     "ctm_env_dims": (ctypes.c_int, [_P, _I, _I, _I, _I]),
     "ctm_svd_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.POINTER(ctypes.c_longlong), _D]),
+    "ctm_debug_poison_allocations": (ctypes.c_int, [ctypes.c_int, _I]),
+    "ctm_debug_guard_violations": (ctypes.c_int, [ctypes.POINTER(ctypes.c_longlong)]),
     "ctm_grad_purification": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.POINTER(ctm_opts), ctypes.c_int,
                                              ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
@@ -271,6 +273,25 @@ def sweep_batch(envs, max_sweeps, tol=0.0, grouped=False):
                             delta.ctypes.data_as(_D))
     envs[0].ctx.check(rc, name)
     return rc, done, delta
+
+
+def poison_allocations(on):
+    """ctm_debug_poison_allocations: while on, every device buffer the library
+    allocates starts as all-ones bytes (NaN doubles), so that reads of memory
+    it never wrote show up in the results, and sits between guard bands that
+    are checked when it is freed (guard_violations()).  Returns the previous
+    state."""
+    prev = ctypes.c_int()
+    load_library().ctm_debug_poison_allocations(1 if on else 0, ctypes.byref(prev))
+    return bool(prev.value)
+
+
+def guard_violations():
+    """ctm_debug_guard_violations: damaged guard bands of poisoned buffers
+    found so far (each is a write past the end of a library buffer)."""
+    n = ctypes.c_longlong()
+    load_library().ctm_debug_guard_violations(ctypes.byref(n))
+    return n.value
 
 
 def _info_dict(info):

@@ -20,3 +20,21 @@ except Exception:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU oracle case")
+
+
+@pytest.fixture(autouse=True)
+def _guard_bands(request):
+    """With poisoned allocations on (CTM_POISON_ALLOC), a GPU test fails if a
+    library buffer freed during it had a damaged guard band (a kernel wrote
+    past the end of a buffer)."""
+    poison = os.environ.get("CTM_POISON_ALLOC", "")
+    if request.node.get_closest_marker("gpu") is None or poison in ("", "0"):
+        yield
+        return
+    from paper_1906_02220_amd import ctm
+    before = ctm.guard_violations()
+    yield
+    import gc
+    gc.collect()
+    after = ctm.guard_violations()
+    assert after == before, "%d guard band(s) damaged during this test" % (after - before)
