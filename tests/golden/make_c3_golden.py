@@ -1,7 +1,14 @@
-"""Write the full-size parity values of the D = 6, chi = 72 workload.
+"""Write the full-size parity values of the D = 6, chi = 72 workload, or of
+the largest member of the ragged batch (D = 7, chi = 96).
 
     python tests/golden/make_c3_golden.py 2    # two sweeps, about 2 minutes on 8 cores
     python tests/golden/make_c3_golden.py 20   # twenty sweeps, about 20 minutes
+    python tests/golden/make_c3_golden.py 2 ragged   # D = 7, chi = 96, about 10 minutes
+
+The ragged member is member 25 of the 32 purifications of the batch
+benchmark ((D, chi) drawn uniformly from {4,5,6,7} x {32,48,72,96} with
+seed 777): seed 778 + 25 = 803, entries drawn in FP32 (then used as FP64);
+it is written to c4_D7_chi96_<sweeps>_sweeps.json with the same fields.
 
 
 Runs the FP64 oracle only (oracle/ctmrg.py): the purification of seed 1234
@@ -44,8 +51,11 @@ def sample_indices(size):
     return (SAMPLE_STRIDE * k + SAMPLE_OFFSET) % size
 
 
-def out_path(sweeps):
-    return os.path.join(HERE, "c3_D6_chi72_%d_sweeps.json" % sweeps)
+RAGGED = {"D": 7, "chi": 96, "seed": 803, "dtype": "float32", "prefix": "c4"}
+
+
+def out_path(sweeps, prefix="c3", d=D, chi=CHI):
+    return os.path.join(HERE, "%s_D%d_chi%d_%d_sweeps.json" % (prefix, d, chi, sweeps))
 
 
 def projections(E8):
@@ -56,9 +66,15 @@ def projections(E8):
     return out
 
 
-def main(SWEEPS):
+def main(SWEEPS, ragged=False):
+    global D, CHI, SEED
+    prefix, dtype = "c3", np.float64
+    if ragged:
+        D, CHI, SEED, prefix, dtype = (RAGGED["D"], RAGGED["chi"], RAGGED["seed"], RAGGED["prefix"],
+                                       np.float32)
     t0 = time.time()
-    A, B = synth.random_purification(D, SEED)
+    A, B = synth.random_purification(D, SEED, dtype=dtype)
+    A, B = A.astype(np.float64), B.astype(np.float64)
     K = O.composite(A, B, GAMMA)
     a = O.double_layer(K)
     arot = [O.rotate(a, k) for k in range(4)]
@@ -80,6 +96,7 @@ def main(SWEEPS):
         "source": "oracle/ctmrg.py via tests/golden/make_c3_golden.py",
         "passage": "arXiv:1906.02220 Sec. III, Figs. 3(a) and 4",
         "D": D, "chi": CHI, "seed": SEED, "gamma": GAMMA, "sweeps": SWEEPS,
+        "entries": "float32" if ragged else "float64",
         "kappa": kap, "energy_bond": e_h,
         "bond_metric_norm": float(np.linalg.norm(E8)),
         "bond_metric_projections": projections(E8),
@@ -93,7 +110,7 @@ def main(SWEEPS):
         "cut_margin_decades_per_move": cut_margin,
         "oracle_seconds": round(time.time() - t0, 1),
     }
-    out = out_path(SWEEPS)
+    out = out_path(SWEEPS, prefix, D, CHI)
     with open(out, "w") as f:
         json.dump(res, f)
     print("wrote %s (kappa %.15g, <H> %.15g, min gap %.6f, %.0f s)" % (
@@ -101,4 +118,4 @@ def main(SWEEPS):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2, len(sys.argv) > 2 and sys.argv[2] == "ragged")

@@ -131,3 +131,48 @@ def test_headline_needs_the_bound_on_both_workloads():
     for m in (1, 3, 4):
         runs[m]["err_kappa_vs_fp64"] = 1e-6
     assert bench.select_headline(runs, st)[:2] == (0, 0.0)
+
+
+def test_mfma_summary_from_counters(tmp_path):
+    """Busy fraction = busy / ((gui_active / xcds) x simds) and 512 flop per
+    MOPS unit, medians over the dispatches of the named kernel only."""
+    path = tmp_path / "c.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for disp, busy, gui, mops in ((1, 512.0, 8.0, 100.0), (2, 256.0, 8.0, 300.0), (3, 768.0, 8.0, 200.0)):
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": "gemm_x<3>", "Counter_Name": "SQ_VALU_MFMA_BUSY_CYCLES", "Counter_Value": busy})
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": "gemm_x<3>", "Counter_Name": "GRBM_GUI_ACTIVE", "Counter_Value": gui})
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": "gemm_x<3>", "Counter_Name": "SQ_INSTS_VALU_MFMA_MOPS_BF16", "Counter_Value": mops})
+        w.writerow({"Dispatch_Id": 9, "Kernel_Name": "other", "Counter_Name": "SQ_VALU_MFMA_BUSY_CYCLES", "Counter_Value": 1e9})
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        profsummary.main(["mfma", "--kernel", "gemm_x", "--counters", str(path), "--simds", "1024", "--xcds", "8",
+                          "--us", "2.0"])
+    kv = dict(line.split(": ", 1) for line in buf.getvalue().splitlines())
+    assert kv["dispatches"] == "3"
+    assert float(kv["mfma_busy_fraction"]) == pytest.approx(0.5)
+    assert float(kv["mfma_flop_per_dispatch_BF16"]) == pytest.approx(200.0 * 512)
+    assert float(kv["mfma_tflops_BF16"]) == pytest.approx(200.0 * 512 / 2e-6 / 1e12)
+
+
+def test_per_move_table_is_the_difference_of_two_traces(tmp_path):
+    import sqlite3
+    def db(path, rows):
+        c = sqlite3.connect(path)
+        c.execute("create table kernels (name text, start integer, end integer)")
+        c.executemany("insert into kernels values (?, ?, ?)", rows)
+        c.commit()
+        c.close()
+    # the short run: 2 x k1 (1 us each), 1 x setup; the long run adds 4 moves
+    # with 2 x k1 (1 us) and 1 x k2 (3 us) each
+    db(tmp_path / "a.db", [("k1(int)", 0, 1000), ("k1(int)", 0, 1000), ("setup(int)", 0, 50000)])
+    db(tmp_path / "b.db", [("k1(int)", 0, 1000)] * 10 + [("k2(int)", 0, 3000)] * 4 + [("setup(int)", 0, 50000)])
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        profsummary.main(["permove", str(tmp_path / "a.db"), str(tmp_path / "b.db"), "4"])
+    lines = {l.split("|")[1].strip(): l.split("|")[2:4] for l in buf.getvalue().splitlines()[2:]}
+    assert float(lines["k2"][0]) == pytest.approx(1.0) and float(lines["k2"][1]) == pytest.approx(3.0)
+    assert float(lines["k1"][0]) == pytest.approx(2.0) and float(lines["k1"][1]) == pytest.approx(2.0)
+    assert "setup" not in lines
+    assert float(lines["total"][1]) == pytest.approx(5.0)
