@@ -284,6 +284,9 @@ constexpr size_t kRedScratchDoubles = 512 + 64;
 
 void fill_zero(Context& ctx, double* p, size_t n);
 void fill_zero_int(Context& ctx, int* p, size_t n);
+// Lets `fn` launch with `bytes` of dynamic LDS (above the 64 KB default, up
+// to the 160 KB of a gfx950 CU); a no-op after the first call per size.
+void allow_lds(const void* fn, size_t bytes);
 void copy_dev(Context& ctx, double* dst, const double* src, size_t n);
 // dst[i * ldd + j] = src[i * lds + j] for i < rows, j < cols (row-major blocks).
 void copy_block(Context& ctx, double* dst, long long ldd, const double* src, long long lds,

@@ -715,24 +715,6 @@ __global__ void spectra_delta_kernel(const double* s, double* old, int chi, doub
   if (threadIdx.x == 0) *delta = dmax;
 }
 
-// Raise the dynamic-LDS limit of a kernel to `bytes` when above the 64 KB
-// default (gfx950 has 160 KB of LDS per CU).
-// Raise a kernel's dynamic-LDS limit once per (kernel, size) and process:
-// later calls, including those made while a stream is being captured into a
-// graph, issue no runtime call.
-void allow_lds(const void* fn, size_t bytes) {
-  if (bytes <= 65536) return;
-  static std::mutex mu;
-  static std::vector<std::pair<const void*, size_t>> done;
-  std::lock_guard<std::mutex> lock(mu);
-  for (auto& e : done)
-    if (e.first == fn && e.second >= bytes) return;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
-    (void)hipGetLastError();
-  else
-    done.push_back({fn, bytes});
-}
-
 inline int grid_for(size_t n, int block = 256, int cap = 4096) {
   size_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -751,6 +733,23 @@ double* red_scratch(Context& ctx) {
 }
 
 }  // namespace
+
+// Raise a kernel's dynamic-LDS limit to `bytes` when above the 64 KB
+// default (gfx950 has 160 KB of LDS per CU), once per (kernel, size) and
+// process: later calls, including those made while a stream is being captured
+// into a graph, issue no runtime call.
+void allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return;
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> done;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : done)
+    if (e.first == fn && e.second >= bytes) return;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    (void)hipGetLastError();
+  else
+    done.push_back({fn, bytes});
+}
 
 void fill_zero(Context& ctx, double* p, size_t n) {
   if (!n) return;

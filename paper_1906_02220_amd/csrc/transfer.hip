@@ -11,10 +11,12 @@
 // vertical one is the same in the frame rotated once (T2, a rotated, T4).
 //
 // The spectrum comes from k steps of Arnoldi on the GPU (classical
-// Gram-Schmidt applied twice, by GEMMs) and the eigenvalues of the k x k
-// Hessenberg matrix by a complex shifted QR iteration (Wilkinson shifts,
-// Givens rotations, deflation at a relative subdiagonal of 2^-52) in one
-// GPU thread.
+// Gram-Schmidt applied twice, by bandwidth-bound projection and update
+// kernels), enqueued without waiting for the device, and the eigenvalues of
+// the k x k Hessenberg matrix by a complex shifted QR iteration (Wilkinson
+// shifts, Givens rotations, deflation at a relative subdiagonal of 2^-52) in
+// one wave.  The 2 chi^2 d^4 product of the site row runs in the
+// environment's precision mode; the rest is FP64.
 
 #include <algorithm>
 #include <cmath>
@@ -43,14 +45,30 @@ __device__ inline cx csqrt_(cx a) {
   return {fabs(a.i) / (2.0 * re), a.i >= 0.0 ? re : -re};
 }
 
-// Eigenvalues of the k x k upper Hessenberg matrix H (row-major, leading
-// dimension ldh) into wr, wi.  Z is k x k complex workspace.  *err = 1 if
-// some eigenvalue did not converge in 200 steps.
-__global__ void hessenberg_eigen_kernel(const double* __restrict__ H, int k, int ldh, cx* Z,
-                                        double* wr, double* wi, int* err) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Z[i * k + j] = {j >= i - 1 ? H[i * ldh + j] : 0.0, 0.0};
+// Eigenvalues of the leading k x k block of the upper Hessenberg matrix H
+// (row-major, leading dimension ldh, kmax columns), where k is kmax or the
+// first j + 1 with H[j + 1][j] exactly zero (an Arnoldi breakdown), into wr,
+// wi, and k into *count.  *err = 1 if some eigenvalue did not converge in 200
+// steps.  One wave: the matrix lives in LDS (k^2 complex entries), every
+// lane takes the same shift and rotation decisions, and each plane rotation
+// updates its two rows (or columns) across the lanes, element by element in
+// the same arithmetic as a serial sweep.
+constexpr int kHessThreads = 64;
+__global__ __launch_bounds__(kHessThreads) void hessenberg_eigen_kernel(
+    const double* __restrict__ H, int kmax, int ldh, double* wr, double* wi, int* err, int* count) {
+  extern __shared__ cx Z[];  // k x k, then the rotations of one QR step
+  const int t = threadIdx.x;
+  int k = kmax;
+  for (int j = 0; j + 1 < kmax; ++j)
+    if (H[(j + 1) * ldh + j] == 0.0) { k = j + 1; break; }
+  cx* cs = Z + (size_t)kmax * kmax;
+  cx* sn = cs + kmax;
+  for (int idx = t; idx < k * k; idx += kHessThreads) {
+    const int i = idx / k, j = idx - (idx / k) * k;
+    Z[idx] = {j >= i - 1 ? H[i * ldh + j] : 0.0, 0.0};
+  }
+  if (t == 0) *count = k;
+  __syncthreads();
   const double eps = 2.220446049250313e-16;
   int hi = k - 1, iter = 0;
   while (hi >= 0) {
@@ -61,19 +79,25 @@ __global__ void hessenberg_eigen_kernel(const double* __restrict__ H, int k, int
       if (sub <= eps * s || sub == 0.0) break;
       --l;
     }
-    if (l > 0) Z[l * k + l - 1] = {0.0, 0.0};
+    __syncthreads();  // every lane has read what decided l
+    if (l > 0 && t == 0) Z[l * k + l - 1] = {0.0, 0.0};
     if (l == hi) {
-      wr[hi] = Z[hi * k + hi].r;
-      wi[hi] = Z[hi * k + hi].i;
+      if (t == 0) {
+        wr[hi] = Z[hi * k + hi].r;
+        wi[hi] = Z[hi * k + hi].i;
+      }
       --hi;
       iter = 0;
+      __syncthreads();
       continue;
     }
     if (++iter > 200) {
-      *err = 1;
-      for (int i = 0; i <= hi; ++i) {
-        wr[i] = Z[i * k + i].r;
-        wi[i] = Z[i * k + i].i;
+      if (t == 0) {
+        *err = 1;
+        for (int i = 0; i <= hi; ++i) {
+          wr[i] = Z[i * k + i].r;
+          wi[i] = Z[i * k + i].i;
+        }
       }
       return;
     }
@@ -90,10 +114,11 @@ __global__ void hessenberg_eigen_kernel(const double* __restrict__ H, int k, int
       const cx m0 = cadd(cscale(cadd(a, d), 0.5), disc), m1 = csub(cscale(cadd(a, d), 0.5), disc);
       mu = cabs_(csub(m0, d)) <= cabs_(csub(m1, d)) ? m0 : m1;
     }
-    for (int i = l; i <= hi; ++i) Z[i * k + i] = csub(Z[i * k + i], mu);
+    __syncthreads();  // the shift is read before the diagonal moves
+    for (int i = l + t; i <= hi; i += kHessThreads) Z[i * k + i] = csub(Z[i * k + i], mu);
+    __syncthreads();
     // Z - mu = Q R by Givens rotations G_i = [[conj c, conj s], [-s, c]] on
     // rows i, i+1; then R Q by G_i^H on columns i, i+1.
-    cx cs[64], sn[64];
     for (int i = l; i < hi; ++i) {
       const cx x = Z[i * k + i], y = Z[(i + 1) * k + i];
       const double r = hypot(cabs_(x), cabs_(y));
@@ -102,36 +127,124 @@ __global__ void hessenberg_eigen_kernel(const double* __restrict__ H, int k, int
         cc = cscale(x, 1.0 / r);
         ss = cscale(y, 1.0 / r);
       }
-      cs[i - l] = cc;
-      sn[i - l] = ss;
-      for (int j = i; j <= hi; ++j) {
+      if (t == 0) {
+        cs[i - l] = cc;
+        sn[i - l] = ss;
+      }
+      __syncthreads();  // x and y are read before lane i rewrites them
+      for (int j = i + t; j <= hi; j += kHessThreads) {
         const cx u = Z[i * k + j], v = Z[(i + 1) * k + j];
         Z[i * k + j] = cadd(cmul(cconj(cc), u), cmul(cconj(ss), v));
         Z[(i + 1) * k + j] = csub(cmul(cc, v), cmul(ss, u));
       }
+      __syncthreads();
     }
     for (int i = l; i < hi; ++i) {
       const cx cc = cs[i - l], ss = sn[i - l];
       const int rmax = min(i + 1, hi);
-      for (int r = l; r <= rmax; ++r) {
+      for (int r = l + t; r <= rmax; r += kHessThreads) {
         const cx u = Z[r * k + i], v = Z[r * k + i + 1];
         Z[r * k + i] = cadd(cmul(u, cc), cmul(v, ss));
         Z[r * k + i + 1] = csub(cmul(v, cconj(cc)), cmul(u, cconj(ss)));
       }
+      __syncthreads();
     }
-    for (int i = l; i <= hi; ++i) Z[i * k + i] = cadd(Z[i * k + i], mu);
+    for (int i = l + t; i <= hi; i += kHessThreads) Z[i * k + i] = cadd(Z[i * k + i], mu);
+    __syncthreads();
   }
 }
 
 // Arnoldi bookkeeping of step j: H[0..j][j] = h1 + h2 (the two Gram-Schmidt
-// passes), H[j+1][j] = ||w|| from nrm2 = w.w, inv = 1 / ||w|| (0 on breakdown).
+// passes), H[j+1][j] = ||w|| from nrm2 = w.w, inv = 1 / ||w||.  At a
+// breakdown (||w|| <= 1e-14 or not finite: an invariant subspace) H[j+1][j]
+// is set to exactly 0 and inv to 0, so that every later basis vector, and
+// with it every later column of H, is exactly zero and the eigenvalue kernel
+// stops at the zero subdiagonal.
 __global__ void arnoldi_step_kernel(double* H, int ldh, int j, const double* h1,
                                     const double* h2, const double* nrm2, double* inv) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int i = 0; i <= j; ++i) H[i * ldh + j] = h1[i] + h2[i];
   const double nv = sqrt(fmax(*nrm2, 0.0));
-  H[(j + 1) * ldh + j] = nv;
-  *inv = nv > 0.0 ? 1.0 / nv : 0.0;
+  const bool ok = nv > 1e-14 && nv < INFINITY;
+  H[(j + 1) * ldh + j] = ok ? nv : 0.0;
+  *inv = ok ? 1.0 / nv : 0.0;
+}
+
+// Classical Gram-Schmidt against the rows V[0..rows) (each dim long, row
+// stride ld) of the Krylov basis, in two kernels each reading V once.
+// Projection: block b writes part[b * 64 + i] = sum over its chunk of
+// V[i][t] w[t] for every row at once (one accumulator per row, one
+// reduction per block); gs_sum_kernel adds the blocks' parts in block order
+// (a fixed order: the result does not depend on scheduling).
+constexpr int kGsMaxRows = 64;
+__global__ __launch_bounds__(256) void gs_project_kernel(const double* __restrict__ V, size_t ld,
+                                                         size_t dim, int rows,
+                                                         const double* __restrict__ w,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4][kGsMaxRows];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t chunk = (dim + gridDim.x - 1) / gridDim.x;
+  const size_t t0 = (size_t)blockIdx.x * chunk;
+  const size_t t1 = t0 + chunk < dim ? t0 + chunk : dim;
+  double a[kGsMaxRows];
+#pragma unroll
+  for (int i = 0; i < kGsMaxRows; ++i) a[i] = 0.0;
+  for (size_t t = t0 + tid; t < t1; t += 256) {
+    const double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < kGsMaxRows; ++i)
+      if (i < rows) a[i] = fma(V[(size_t)i * ld + t], wt, a[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kGsMaxRows; ++i) {
+    if (i < rows) {
+      double v = a[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[wave][i] = v;
+    }
+  }
+  __syncthreads();
+  if (tid < rows)
+    part[(size_t)blockIdx.x * kGsMaxRows + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// h[i] = sum over the blocks b of part[b * 64 + i]: four threads per row take
+// every fourth block with four independent accumulators, then the sixteen
+// partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void gs_sum_kernel(const double* __restrict__ part, int nblk,
+                                                     int rows, double* __restrict__ h) {
+  __shared__ double sh[4][kGsMaxRows];
+  const int i = threadIdx.x & (kGsMaxRows - 1), q = threadIdx.x >> 6;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (i < rows) {
+    int b = q;
+    for (; b + 12 < nblk; b += 16) {
+      s0 += part[(size_t)b * kGsMaxRows + i];
+      s1 += part[(size_t)(b + 4) * kGsMaxRows + i];
+      s2 += part[(size_t)(b + 8) * kGsMaxRows + i];
+      s3 += part[(size_t)(b + 12) * kGsMaxRows + i];
+    }
+    for (; b < nblk; b += 4) s0 += part[(size_t)b * kGsMaxRows + i];
+  }
+  sh[q][i] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (q == 0 && i < rows) h[i] = (sh[0][i] + sh[1][i]) + (sh[2][i] + sh[3][i]);
+}
+
+// w[t] -= sum_i V[i][t] h[i] for i < rows.
+__global__ __launch_bounds__(256) void gs_update_kernel(const double* __restrict__ V, size_t ld,
+                                                        size_t dim, int rows,
+                                                        const double* __restrict__ h,
+                                                        double* __restrict__ w) {
+  __shared__ double hs[kGsMaxRows];
+  if (threadIdx.x < rows) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < dim; t += (size_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int i = 0; i < rows; ++i) s = fma(V[(size_t)i * ld + t], hs[i], s);
+    w[t] -= s;
+  }
 }
 
 // inv = 1 / sqrt(nrm2) (0 if nrm2 is 0)
@@ -184,7 +297,13 @@ void Transfer::apply(const double* v, double* out) {
     const long long q4[4] = {chi, d, chi, d};
     const int p0213[4] = {0, 2, 1, 3};
     permute(ctx, w1.d(), w2.d(), 4, q4, p0213);  // [x][y'][l][n]
-    mm(ctx, chi * chi, d * d, d * d, w2.d(), d * d, false, aT.d(), d * d, false, w1.d(), d * d);
+    // the 2 chi^2 d^4 product in the environment's precision mode (the site
+    // tensor's slices are cut once per Transfer)
+    const int M = chi * chi, N = d * d, K = d * d;
+    if (!gemm_slices_split_out(ctx, e.opt.precision, M, N, K, rowmajor(w2.d(), K),
+                               rowmajor(aT.d(), N), w1.d(), OutMap::plain(M, N, N), -1, &aslices))
+      gemm_mixed(ctx, e.opt.precision, M, N, K, 1.0, rowmajor(w2.d(), K), rowmajor(aT.d(), N), 0.0,
+                 out_rowmajor(w1.d(), N));
     const int p0231[4] = {0, 2, 3, 1};
     const long long r4[4] = {chi, chi, d, d};
     permute(ctx, w1.d(), w2.d(), 4, r4, p0231);  // [x][m][r][y']
@@ -200,15 +319,17 @@ void Transfer::apply(const double* v, double* out) {
 
 int Transfer::spectrum(int krylov, unsigned long long seed, double* wr_out, double* wi_out) {
   const int k = (int)std::min<size_t>((size_t)std::max(krylov, 2), std::min<size_t>(dim, 64));
+  static_assert(kGsMaxRows >= 64, "Gram-Schmidt rows");
   DevBuf V((size_t)(k + 1) * dim * sizeof(double));
   DevBuf H((size_t)(k + 1) * k * sizeof(double));
   DevBuf h(2 * (size_t)(k + 1) * sizeof(double));
+  const int gblk = (int)std::min<size_t>((dim + 255) / 256, 512);
+  DevBuf part((size_t)gblk * kGsMaxRows * sizeof(double));
   DevBuf sc(4 * sizeof(double));
-  DevBuf Z((size_t)k * k * sizeof(cx));
   DevBuf wr(k * sizeof(double)), wi(k * sizeof(double));
-  DevBuf err(sizeof(int));
+  DevBuf flags(2 * sizeof(int));  // error, number of Ritz values
   fill_zero(ctx, H.d(), (size_t)(k + 1) * k);
-  fill_zero_int(ctx, (int*)err.p, 1);
+  fill_zero_int(ctx, (int*)flags.p, 2);
   double* v0 = V.d();
   fill_normal(ctx, v0, dim, seed, 0);
   dot(ctx, v0, v0, dim, sc.d());
@@ -216,7 +337,8 @@ int Transfer::spectrum(int krylov, unsigned long long seed, double* wr_out, doub
   hipLaunchKernelGGL(scale_dev_kernel, dim3(nblk(dim)), dim3(256), 0, ctx.stream, v0, dim,
                      sc.d() + 1);
   CTM_HIP(hipGetLastError());
-  int steps = k;
+  // k steps without waiting for the device: a breakdown zeroes the rest of
+  // the basis (arnoldi_step_kernel) instead of stopping the loop
   for (int j = 0; j < k; ++j) {
     double* vj = V.d() + (size_t)j * dim;
     double* w = V.d() + (size_t)(j + 1) * dim;
@@ -224,34 +346,35 @@ int Transfer::spectrum(int krylov, unsigned long long seed, double* wr_out, doub
     // two passes of classical Gram-Schmidt against v_0..v_j
     double* h1 = h.d();
     double* h2 = h.d() + (k + 1);
-    mm(ctx, j + 1, 1, (int)dim, V.d(), dim, false, w, 1, false, h1, 1);
-    mm(ctx, (int)dim, 1, j + 1, V.d(), dim, true, h1, 1, false, w, 1, 1.0, -1.0);
-    mm(ctx, j + 1, 1, (int)dim, V.d(), dim, false, w, 1, false, h2, 1);
-    mm(ctx, (int)dim, 1, j + 1, V.d(), dim, true, h2, 1, false, w, 1, 1.0, -1.0);
+    for (int pass = 0; pass < 2; ++pass) {
+      double* hp = pass == 0 ? h1 : h2;
+      hipLaunchKernelGGL(gs_project_kernel, dim3(gblk), dim3(256), 0, ctx.stream, V.d(), dim, dim,
+                         j + 1, w, part.d());
+      hipLaunchKernelGGL(gs_sum_kernel, dim3(1), dim3(256), 0, ctx.stream, part.d(), gblk, j + 1,
+                         hp);
+      hipLaunchKernelGGL(gs_update_kernel, dim3(nblk(dim)), dim3(256), 0, ctx.stream, V.d(), dim,
+                         dim, j + 1, hp, w);
+    }
     dot(ctx, w, w, dim, sc.d());
     hipLaunchKernelGGL(arnoldi_step_kernel, dim3(1), dim3(1), 0, ctx.stream, H.d(), k, j, h1, h2,
                        sc.d(), sc.d() + 1);
     hipLaunchKernelGGL(scale_dev_kernel, dim3(nblk(dim)), dim3(256), 0, ctx.stream, w, dim,
                        sc.d() + 1);
     CTM_HIP(hipGetLastError());
-    double hn = 0.0;
-    CTM_HIP(hipMemcpyAsync(&hn, H.d() + (size_t)(j + 1) * k + j, sizeof(double),
-                           hipMemcpyDeviceToHost, ctx.stream));
-    CTM_HIP(hipStreamSynchronize(ctx.stream));
-    if (!(hn > 1e-14) || !std::isfinite(hn)) {  // invariant subspace (or breakdown)
-      steps = j + 1;
-      break;
-    }
   }
-  hipLaunchKernelGGL(hessenberg_eigen_kernel, dim3(1), dim3(1), 0, ctx.stream, H.d(), steps, k,
-                     (cx*)Z.p, wr.d(), wi.d(), (int*)err.p);
+  const size_t hlds = ((size_t)k * k + 2 * (size_t)k) * sizeof(cx);
+  allow_lds((const void*)hessenberg_eigen_kernel, hlds);
+  hipLaunchKernelGGL(hessenberg_eigen_kernel, dim3(1), dim3(kHessThreads), hlds, ctx.stream, H.d(),
+                     k, k, wr.d(), wi.d(), (int*)flags.p, (int*)flags.p + 1);
   CTM_HIP(hipGetLastError());
-  int herr = 0;
-  CTM_HIP(hipMemcpyAsync(wr_out, wr.p, steps * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  CTM_HIP(hipMemcpyAsync(wi_out, wi.p, steps * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  CTM_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+  int hf[2] = {0, 0};
+  CTM_HIP(hipMemcpyAsync(hf, flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
   CTM_HIP(hipStreamSynchronize(ctx.stream));
-  if (herr) throw Error(-4, "transfer spectrum: Hessenberg QR did not converge");
+  const int steps = hf[1];
+  CTM_REQUIRE(steps >= 1 && steps <= k, "transfer spectrum: bad Ritz value count");
+  CTM_HIP(hipMemcpy(wr_out, wr.p, steps * sizeof(double), hipMemcpyDeviceToHost));
+  CTM_HIP(hipMemcpy(wi_out, wi.p, steps * sizeof(double), hipMemcpyDeviceToHost));
+  if (hf[0]) throw Error(-4, "transfer spectrum: Hessenberg QR did not converge");
   return steps;
 }
 

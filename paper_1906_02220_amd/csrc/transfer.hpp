@@ -22,6 +22,7 @@ class Transfer {
   bool site;
   int chi, d;
   DevBuf w1, w2, aT;
+  SliceCache aslices;  // BF16 slices of aT (reduced-precision modes)
 };
 
 }  // namespace ctm
