@@ -344,6 +344,29 @@ int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm
                     double w_expect, double* log_kappa, double* expect, double* grad_a,
                     ctm_grad_info* info);
 
+/* The same two gradients with A, B (a) and grad_A, grad_B (grad_a) in device
+ * memory of the context's device, for callers whose tensors already live
+ * there (torch autograd): nothing crosses PCIe but the scalars and, when
+ * given, the small host arrays op (16 x 16 or 4 x 4) and a_imp.  The inputs
+ * are read and the gradients written on the context's stream, and the call
+ * returns after that stream has drained, so the caller must have finished
+ * writing the inputs (on any stream) before the call.  Each device pointer
+ * must lie in one device allocation of the context's device holding the
+ * whole array (CTM_EINVAL otherwise, nothing written; an allocator that
+ * sub-allocates, like torch's caching allocator, is seen as its underlying
+ * segment, so only overruns past that segment are caught); the layouts are
+ * those of the host calls. */
+int ctm_grad_purification_dev(ctm_context* ctx, const double* A, const double* B, int D,
+                              int D_gamma, int gamma, int chi, const ctm_opts* opts, int sweeps,
+                              int checkpoint_every, const double* op, int op_dim,
+                              double w_log_kappa, double w_expect, double* log_kappa,
+                              double* expect, double* grad_A, double* grad_B,
+                              ctm_grad_info* info);
+int ctm_grad_tensor_dev(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                        int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
+                        double w_expect, double* log_kappa, double* expect, double* grad_a,
+                        ctm_grad_info* info);
+
 /* One bond update of the exact-environment full update (Sec. III,
  * Fig. 3(b), Fig. 4).  The gate exp(-tau H/2) of the real 4 x 4 bond term H
  * (row-major, index (s_A s_B)(s_A' s_B'), acting on the pseudospins) is

@@ -6,8 +6,10 @@ after `sweeps` sweeps (ctm_grad_purification); calling ``backward()`` on
 anything computed from it propagates the library's dL/dA and dL/dB, scaled by
 the incoming gradient.  ``tensor_objective`` is the same for a site tensor
 (ctm_grad_tensor).  The forward call computes the gradient as well (one
-library call does both), and the tensors are exchanged as host FP64 arrays:
-this module only marshals arguments.
+library call does both).  Tensors in GPU memory go to the library as device
+pointers (ctm_grad_purification_dev, ctm_grad_tensor_dev) and their
+gradients come back in GPU memory; other tensors are exchanged as host FP64
+arrays.  This module only marshals arguments.
 """
 import numpy as np
 import torch
@@ -19,15 +21,25 @@ def _host(t):
     return t.detach().to("cpu", torch.float64).contiguous().numpy()
 
 
+def _lib_input(t):
+    """A GPU tensor goes to the library as is (device-pointer path), any
+    other as a host FP64 array."""
+    return t.detach() if t.is_cuda else _host(t)
+
+
+def _as_grad(g, like):
+    g = g if torch.is_tensor(g) else torch.from_numpy(g)
+    return g.to(like.device, like.dtype)
+
+
 class _PurificationObjective(torch.autograd.Function):
     @staticmethod
     def forward(fctx, A, B, context, gamma, chi, sweeps, op, w_log_kappa, w_expect,
                 checkpoint_every, opts):
         lk, ex, gA, gB, info = ctm.grad_purification(
-            context, _host(A), _host(B), gamma, chi, sweeps, op=op, w_log_kappa=w_log_kappa,
-            w_expect=w_expect, checkpoint_every=checkpoint_every, **opts)
-        fctx.save_for_backward(torch.from_numpy(gA).to(A.device, A.dtype),
-                               torch.from_numpy(gB).to(B.device, B.dtype))
+            context, _lib_input(A), _lib_input(B), gamma, chi, sweeps, op=op,
+            w_log_kappa=w_log_kappa, w_expect=w_expect, checkpoint_every=checkpoint_every, **opts)
+        fctx.save_for_backward(_as_grad(gA, A), _as_grad(gB, B))
         fctx.info = info
         return A.new_tensor(w_log_kappa * lk + w_expect * ex)
 
@@ -42,9 +54,9 @@ class _TensorObjective(torch.autograd.Function):
     def forward(fctx, a, context, chi, sweeps, a_imp, w_log_kappa, w_expect, checkpoint_every,
                 opts):
         lk, ex, ga, info = ctm.grad_tensor(
-            context, _host(a), chi, sweeps, a_imp=a_imp, w_log_kappa=w_log_kappa,
+            context, _lib_input(a), chi, sweeps, a_imp=a_imp, w_log_kappa=w_log_kappa,
             w_expect=w_expect, checkpoint_every=checkpoint_every, **opts)
-        fctx.save_for_backward(torch.from_numpy(ga).to(a.device, a.dtype))
+        fctx.save_for_backward(_as_grad(ga, a))
         fctx.info = info
         return a.new_tensor(w_log_kappa * lk + w_expect * ex)
 

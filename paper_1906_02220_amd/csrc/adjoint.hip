@@ -882,15 +882,14 @@ void Grad::site_total() {
   site_done = true;
 }
 
-void Grad::grad_site(double* ga) {
+void Grad::grad_site(double* ga_dev) {
   site_total();
   const size_t d4 = (size_t)d * d * d * d;
-  CTM_HIP(hipMemcpyAsync(ga, abar.p, d4 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  CTM_HIP(hipStreamSynchronize(ctx.stream));
+  copy_dev(ctx, ga_dev, abar.d(), d4);
 }
 
-void Grad::grad_purification(const double* A, const double* B, int D, int Dg, int gamma,
-                             double* gA, double* gB) {
+void Grad::grad_purification(const double* A_dev, const double* B_dev, int D, int Dg, int gamma,
+                             double* gA_dev, double* gB_dev) {
   CTM_REQUIRE(e.D == D && D * D == d, "grad_purification: not this environment's purification");
   site_total();
   const int D4 = D * D * D * D;
@@ -917,18 +916,15 @@ void Grad::grad_purification(const double* A, const double* B, int D, int Dg, in
   long long pd[5];
   for (int a = 0; a < 5; ++a) pd[a] = dims[perm5[a]];
   const size_t sz = 4ull * D * D * Dg;
-  DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double)), Ap(sz * sizeof(double)),
-      Bp(sz * sizeof(double)), Apb(sz * sizeof(double)), Bpb(sz * sizeof(double));
-  CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  permute(ctx, dA.d(), Ap.d(), 5, dims, perm5);
-  permute(ctx, dB.d(), Bp.d(), 5, dims, perm5);
+  DevBuf Ap(sz * sizeof(double)), Bp(sz * sizeof(double)), Apb(sz * sizeof(double)),
+      Bpb(sz * sizeof(double));
+  permute(ctx, A_dev, Ap.d(), 5, dims, perm5);
+  permute(ctx, B_dev, Bp.d(), 5, dims, perm5);
   mm(ctx, m4, Dg, m4, Krb.d(), m4, false, Bp.d(), Dg, false, Apb.d(), Dg);
   mm(ctx, m4, Dg, m4, Krb.d(), m4, true, Ap.d(), Dg, false, Bpb.d(), Dg);
-  permute(ctx, Apb.d(), dA.d(), 5, pd, inv5);
-  permute(ctx, Bpb.d(), dB.d(), 5, pd, inv5);
-  CTM_HIP(hipMemcpyAsync(gA, dA.p, sz * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  CTM_HIP(hipMemcpyAsync(gB, dB.p, sz * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  permute(ctx, Apb.d(), gA_dev, 5, pd, inv5);
+  permute(ctx, Bpb.d(), gB_dev, 5, pd, inv5);
+  // the temporaries are freed on return: let the stream finish with them
   CTM_HIP(hipStreamSynchronize(ctx.stream));
 }
 

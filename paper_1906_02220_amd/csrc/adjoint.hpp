@@ -26,11 +26,12 @@ class Grad {
   double seed(double w_k, double w_o, const double* op, int op_dim, const double* a_imp,
               double* log_kappa, double* expect);
   void backward();
-  // dL/da, a[u][l][d][r] (host, d^4)
-  void grad_site(double* ga);
-  // dL/dA, dL/dB in the layout of the inputs (host, 4 D^2 D_gamma each)
-  void grad_purification(const double* A, const double* B, int D, int Dg, int gamma, double* gA,
-                         double* gB);
+  // dL/da, a[u][l][d][r] (device, d^4), written on ctx.stream
+  void grad_site(double* ga_dev);
+  // dL/dA, dL/dB in the layout of the inputs (device arrays of 4 D^2 D_gamma
+  // each, read and written on ctx.stream)
+  void grad_purification(const double* A_dev, const double* B_dev, int D, int Dg, int gamma,
+                         double* gA_dev, double* gB_dev);
   GradStats stats;
 
  private:

@@ -467,11 +467,11 @@ void fill_info(const ctm::GradStats& g, ctm_grad_info* info) {
 
 }  // namespace
 
-int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, int D, int D_gamma,
-                          int gamma, int chi, const ctm_opts* opts, int sweeps,
-                          int checkpoint_every, const double* op, int op_dim,
-                          double w_log_kappa, double w_expect, double* log_kappa,
-                          double* expect, double* grad_A, double* grad_B, ctm_grad_info* info) {
+static int grad_purification(ctm_context* ctx, const double* A, const double* B, int D, int D_gamma,
+                             int gamma, int chi, const ctm_opts* opts, int sweeps,
+                             int checkpoint_every, const double* op, int op_dim, double w_log_kappa,
+                             double w_expect, double* log_kappa, double* expect, double* grad_A,
+                             double* grad_B, ctm_grad_info* info, bool on_device) {
   if (!ctx) return CTM_EINVAL;
   return guarded(ctx, [&] {
     CTM_REQUIRE(A && B && grad_A && grad_B, "null argument");
@@ -482,23 +482,112 @@ int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, in
     CTM_REQUIRE(op || w_expect == 0.0, "w_expect needs an operator");
     CTM_REQUIRE(!op || op_dim == 4 || op_dim == 16, "op_dim must be 4 or 16");
     const int d = D * D;
+    const size_t sz = 4ull * D * D * D_gamma;
+    if (on_device) {
+      check_device_array(ctx->c, A, sz * sizeof(double), "A");
+      check_device_array(ctx->c, B, sz * sizeof(double), "B");
+      check_device_array(ctx->c, grad_A, sz * sizeof(double), "grad_A");
+      check_device_array(ctx->c, grad_B, sz * sizeof(double), "grad_B");
+    }
     ctm::EnvOptions o = gradient_options(opts, d);
     CTM_HIP(hipSetDevice(ctx->c.device));
     ctm::Env env(ctx->c, d, chi, o);
-    const size_t sz = 4ull * D * D * D_gamma;
-    {
-      ctm::DevBuf dA(sz * sizeof(double)), dB(sz * sizeof(double));
+    // device copies of host inputs (and of the gradients for host outputs)
+    ctm::DevBuf dA, dB, gA, gB;
+    const double *sA = A, *sB = B;
+    double *tA = grad_A, *tB = grad_B;
+    if (!on_device) {
+      dA.alloc(sz * sizeof(double));
+      dB.alloc(sz * sizeof(double));
+      gA.alloc(sz * sizeof(double));
+      gB.alloc(sz * sizeof(double));
       CTM_HIP(hipMemcpyAsync(dA.p, A, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
       CTM_HIP(hipMemcpyAsync(dB.p, B, sz * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
-      env.build_purification_dev(dA.d(), dB.d(), D, D_gamma, gamma);
+      sA = dA.d();
+      sB = dB.d();
+      tA = gA.d();
+      tB = gB.d();
     }
+    env.build_purification_dev(sA, sB, D, D_gamma, gamma);
     env.init_boundary();
     ctm::Grad g(env, sweeps, checkpoint_every);
     g.forward();
     double lk = 0.0, ex = 0.0;
     g.seed(w_log_kappa, w_expect, op, op_dim, nullptr, &lk, &ex);
     g.backward();
-    g.grad_purification(A, B, D, D_gamma, gamma, grad_A, grad_B);
+    g.grad_purification(sA, sB, D, D_gamma, gamma, tA, tB);
+    if (!on_device) {
+      CTM_HIP(hipMemcpyAsync(grad_A, gA.p, sz * sizeof(double), hipMemcpyDeviceToHost, ctx->c.stream));
+      CTM_HIP(hipMemcpyAsync(grad_B, gB.p, sz * sizeof(double), hipMemcpyDeviceToHost, ctx->c.stream));
+    }
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    if (log_kappa) *log_kappa = lk;
+    if (expect) *expect = ex;
+    fill_info(g.stats, info);
+  });
+}
+
+int ctm_grad_purification(ctm_context* ctx, const double* A, const double* B, int D, int D_gamma,
+                          int gamma, int chi, const ctm_opts* opts, int sweeps,
+                          int checkpoint_every, const double* op, int op_dim,
+                          double w_log_kappa, double w_expect, double* log_kappa,
+                          double* expect, double* grad_A, double* grad_B, ctm_grad_info* info) {
+  return grad_purification(ctx, A, B, D, D_gamma, gamma, chi, opts, sweeps, checkpoint_every, op,
+                           op_dim, w_log_kappa, w_expect, log_kappa, expect, grad_A, grad_B, info,
+                           false);
+}
+
+int ctm_grad_purification_dev(ctm_context* ctx, const double* A, const double* B, int D,
+                              int D_gamma, int gamma, int chi, const ctm_opts* opts, int sweeps,
+                              int checkpoint_every, const double* op, int op_dim,
+                              double w_log_kappa, double w_expect, double* log_kappa,
+                              double* expect, double* grad_A, double* grad_B,
+                              ctm_grad_info* info) {
+  return grad_purification(ctx, A, B, D, D_gamma, gamma, chi, opts, sweeps, checkpoint_every, op,
+                           op_dim, w_log_kappa, w_expect, log_kappa, expect, grad_A, grad_B, info,
+                           true);
+}
+
+static int grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                       int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
+                       double w_expect, double* log_kappa, double* expect, double* grad_a,
+                       ctm_grad_info* info, bool on_device) {
+  if (!ctx) return CTM_EINVAL;
+  return guarded(ctx, [&] {
+    CTM_REQUIRE(a && grad_a, "null argument");
+    CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
+    CTM_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
+    CTM_REQUIRE(a_imp || w_expect == 0.0, "w_expect needs an impurity tensor");
+    const size_t d4 = (size_t)d * d * d * d;
+    if (on_device) {
+      check_device_array(ctx->c, a, d4 * sizeof(double), "a");
+      check_device_array(ctx->c, grad_a, d4 * sizeof(double), "grad_a");
+    }
+    ctm::EnvOptions o = gradient_options(opts, d);
+    CTM_HIP(hipSetDevice(ctx->c.device));
+    ctm::Env env(ctx->c, d, chi, o);
+    ctm::DevBuf da, ga;
+    const double* sa = a;
+    double* ta = grad_a;
+    if (!on_device) {
+      da.alloc(d4 * sizeof(double));
+      ga.alloc(d4 * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
+      sa = da.d();
+      ta = ga.d();
+    }
+    env.set_site_tensor_dev(sa);
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
+    env.init_boundary();
+    ctm::Grad g(env, sweeps, checkpoint_every);
+    g.forward();
+    double lk = 0.0, ex = 0.0;
+    g.seed(w_log_kappa, w_expect, nullptr, 0, a_imp, &lk, &ex);
+    g.backward();
+    g.grad_site(ta);
+    if (!on_device)
+      CTM_HIP(hipMemcpyAsync(grad_a, ga.p, d4 * sizeof(double), hipMemcpyDeviceToHost, ctx->c.stream));
+    CTM_HIP(hipStreamSynchronize(ctx->c.stream));
     if (log_kappa) *log_kappa = lk;
     if (expect) *expect = ex;
     fill_info(g.stats, info);
@@ -509,33 +598,16 @@ int ctm_grad_tensor(ctm_context* ctx, const double* a, int d, int chi, const ctm
                     int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
                     double w_expect, double* log_kappa, double* expect, double* grad_a,
                     ctm_grad_info* info) {
-  if (!ctx) return CTM_EINVAL;
-  return guarded(ctx, [&] {
-    CTM_REQUIRE(a && grad_a, "null argument");
-    CTM_REQUIRE(d >= 1 && chi >= 1, "d and chi must be >= 1");
-    CTM_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
-    CTM_REQUIRE(a_imp || w_expect == 0.0, "w_expect needs an impurity tensor");
-    ctm::EnvOptions o = gradient_options(opts, d);
-    CTM_HIP(hipSetDevice(ctx->c.device));
-    ctm::Env env(ctx->c, d, chi, o);
-    const size_t d4 = (size_t)d * d * d * d;
-    {
-      ctm::DevBuf da(d4 * sizeof(double));
-      CTM_HIP(hipMemcpyAsync(da.p, a, d4 * sizeof(double), hipMemcpyHostToDevice, ctx->c.stream));
-      env.set_site_tensor_dev(da.d());
-      CTM_HIP(hipStreamSynchronize(ctx->c.stream));
-    }
-    env.init_boundary();
-    ctm::Grad g(env, sweeps, checkpoint_every);
-    g.forward();
-    double lk = 0.0, ex = 0.0;
-    g.seed(w_log_kappa, w_expect, nullptr, 0, a_imp, &lk, &ex);
-    g.backward();
-    g.grad_site(grad_a);
-    if (log_kappa) *log_kappa = lk;
-    if (expect) *expect = ex;
-    fill_info(g.stats, info);
-  });
+  return grad_tensor(ctx, a, d, chi, opts, sweeps, checkpoint_every, a_imp, w_log_kappa, w_expect,
+                     log_kappa, expect, grad_a, info, false);
+}
+
+int ctm_grad_tensor_dev(ctm_context* ctx, const double* a, int d, int chi, const ctm_opts* opts,
+                        int sweeps, int checkpoint_every, const double* a_imp, double w_log_kappa,
+                        double w_expect, double* log_kappa, double* expect, double* grad_a,
+                        ctm_grad_info* info) {
+  return grad_tensor(ctx, a, d, chi, opts, sweeps, checkpoint_every, a_imp, w_log_kappa, w_expect,
+                     log_kappa, expect, grad_a, info, true);
 }
 
 int ctm_fu_bond_update(ctm_context* ctx, const double* A, const double* B, int D, int gamma,

@@ -121,6 +121,16 @@ SIGNATURES = {
                                        ctypes.POINTER(ctm_opts), ctypes.c_int, ctypes.c_int, _D,
                                        ctypes.c_double, ctypes.c_double, _D, _D, _D,
                                        ctypes.POINTER(ctm_grad_info)]),
+    "ctm_grad_purification_dev": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctm_opts), ctypes.c_int,
+                                                 ctypes.c_int, _D, ctypes.c_int, ctypes.c_double,
+                                                 ctypes.c_double, _D, _D, _P, _P,
+                                                 ctypes.POINTER(ctm_grad_info)]),
+    "ctm_grad_tensor_dev": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctm_opts), ctypes.c_int, ctypes.c_int,
+                                           _D, ctypes.c_double, ctypes.c_double, _D, _D, _P,
+                                           ctypes.POINTER(ctm_grad_info)]),
     "ctm_fu_bond_update": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int, _D,
                                           ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctm_opts),
                                           ctypes.c_int, ctypes.c_int, _D, _D, _D]),
@@ -301,7 +311,13 @@ def _info_dict(info):
 def grad_purification(ctx, A, B, gamma, chi, sweeps, op=None, w_log_kappa=1.0, w_expect=0.0,
                       checkpoint_every=0, **kw):
     """ctm_grad_purification: gradient of w_log_kappa ln(kappa) + w_expect <op>
-    after `sweeps` sweeps.  Returns (log_kappa, expect, dA, dB, info)."""
+    after `sweeps` sweeps.  Returns (log_kappa, expect, dA, dB, info).  With
+    A and B torch tensors in GPU memory the call goes through
+    ctm_grad_purification_dev and dA, dB are FP64 torch tensors on that GPU;
+    otherwise they are NumPy arrays."""
+    if _on_gpu(A) and _on_gpu(B):
+        return _grad_purification_dev(ctx, A, B, gamma, chi, sweeps, op, w_log_kappa, w_expect,
+                                      checkpoint_every, **kw)
     A = _f64(A)
     B = _f64(B)
     if A.shape != B.shape or A.ndim != 5 or A.shape[:2] != (2, 2):
@@ -330,16 +346,66 @@ def grad_purification(ctx, A, B, gamma, chi, sweeps, op=None, w_log_kappa=1.0, w
     return lk.value, ex.value, gA, gB, _info_dict(info)
 
 
+def _grad_purification_dev(ctx, A, B, gamma, chi, sweeps, op, w_log_kappa, w_expect,
+                           checkpoint_every, **kw):
+    import torch
+    A = _gpu_f64(A)
+    B = _gpu_f64(B)
+    if A.shape != B.shape or A.dim() != 5 or tuple(A.shape[:2]) != (2, 2):
+        raise ValueError("A and B must both have shape (2, 2, Dx, Dy, Dz)")
+    dims = list(A.shape[2:])
+    Dg = dims[gamma]
+    rest = [dims[i] for i in range(3) if i != gamma]
+    if rest[0] != rest[1]:
+        raise ValueError("the two non-fused bonds must share one dimension D")
+    o = default_opts(**kw)
+    opp, op_dim = None, 0
+    if op is not None:
+        opp = _f64(op.detach().cpu().numpy() if torch.is_tensor(op) else op)
+        op_dim = opp.shape[0]
+    gA = torch.empty_like(A)
+    gB = torch.empty_like(B)
+    lk = ctypes.c_double()
+    ex = ctypes.c_double()
+    info = ctm_grad_info()
+    rc = ctx.lib.ctm_grad_purification_dev(
+        ctx.h, _P(A.data_ptr()), _P(B.data_ptr()), rest[0], Dg, gamma, chi, ctypes.byref(o), sweeps,
+        checkpoint_every, _dptr(opp) if opp is not None else None, op_dim, w_log_kappa, w_expect,
+        ctypes.byref(lk), ctypes.byref(ex), _P(gA.data_ptr()), _P(gB.data_ptr()), ctypes.byref(info))
+    ctx.check(rc, "ctm_grad_purification_dev")
+    return lk.value, ex.value, gA, gB, _info_dict(info)
+
+
 def grad_tensor(ctx, a, chi, sweeps, a_imp=None, w_log_kappa=1.0, w_expect=0.0,
                 checkpoint_every=0, **kw):
     """ctm_grad_tensor: gradient of w_log_kappa ln(kappa) + w_expect <E,a_imp>/<E,a>
-    with respect to the site tensor a.  Returns (log_kappa, expect, da, info)."""
-    a = _f64(a)
+    with respect to the site tensor a.  Returns (log_kappa, expect, da, info).
+    With a a torch tensor in GPU memory the call goes through
+    ctm_grad_tensor_dev and da is an FP64 torch tensor on that GPU."""
+    dev = _on_gpu(a)
+    if dev:
+        import torch
+        a = _gpu_f64(a)
+        if torch.is_tensor(a_imp):
+            a_imp = a_imp.detach().cpu().numpy()
+    else:
+        a = _f64(a)
     d = a.shape[0]
-    if a.shape != (d, d, d, d):
+    if tuple(a.shape) != (d, d, d, d):
         raise ValueError("a must have shape (d, d, d, d)")
     o = default_opts(**kw)
     ai = _f64(a_imp) if a_imp is not None else None
+    lk = ctypes.c_double()
+    ex = ctypes.c_double()
+    info = ctm_grad_info()
+    if dev:
+        ga = torch.empty_like(a)
+        rc = ctx.lib.ctm_grad_tensor_dev(ctx.h, _P(a.data_ptr()), d, chi, ctypes.byref(o), sweeps,
+                                         checkpoint_every, _dptr(ai) if ai is not None else None,
+                                         w_log_kappa, w_expect, ctypes.byref(lk), ctypes.byref(ex),
+                                         _P(ga.data_ptr()), ctypes.byref(info))
+        ctx.check(rc, "ctm_grad_tensor_dev")
+        return lk.value, ex.value, ga, _info_dict(info)
     ga = np.zeros_like(a)
     lk = ctypes.c_double()
     ex = ctypes.c_double()

@@ -7,6 +7,7 @@ workload), plus properties that hold at any size (Euler homogeneity,
 invariance under a gauge of the fused bond) and closed-form Ising
 correlations, which are derivatives of the free energy.
 """
+import ctypes
 import json
 import os
 import sys
@@ -262,3 +263,46 @@ def test_torch_autograd_function(ctx):
     La.backward()
     lk, ex, ga, _ = ctm.grad_tensor(ctx, synth.ising_square_tensor(0.4), 8, 10)
     assert np.array_equal(a.grad.numpy(), ga)
+
+
+def test_device_pointer_gradients_match_the_host_path(ctx):
+    """ctm_grad_purification_dev and ctm_grad_tensor_dev (torch tensors in GPU
+    memory, gradients written there) give the host calls' gradients bit for
+    bit; the autograd binding takes that path for GPU tensors; host memory
+    passed as a device array is refused."""
+    import torch
+    from paper_1906_02220_amd import autograd as AG
+    say("case: device-pointer gradients D=3 chi=12 and Ising chi=8")
+    A, B = synth.random_purification(3, 17)
+    lk, ex, gA, gB, _ = ctm.grad_purification(ctx, A, B, 2, 12, 6, op=H, w_log_kappa=1.0,
+                                              w_expect=0.5)
+    At = torch.tensor(A, device="cuda")
+    Bt = torch.tensor(B, device="cuda")
+    lk2, ex2, gA2, gB2, _ = ctm.grad_purification(ctx, At, Bt, 2, 12, 6, op=H, w_log_kappa=1.0,
+                                                  w_expect=0.5)
+    assert gA2.is_cuda and gB2.is_cuda
+    assert lk2 == lk and ex2 == ex
+    assert np.array_equal(gA2.cpu().numpy(), gA) and np.array_equal(gB2.cpu().numpy(), gB)
+    # autograd with GPU leaves: the same gradient, left on the GPU
+    Al = At.clone().requires_grad_(True)
+    Bl = Bt.clone().requires_grad_(True)
+    L = AG.purification_objective(ctx, Al, Bl, 2, 12, 6, op=H, w_log_kappa=1.0, w_expect=0.5)
+    L.backward()
+    assert Al.grad.is_cuda and np.array_equal(Al.grad.cpu().numpy(), gA)
+    a = synth.ising_square_tensor(0.4)
+    lk, ex, ga, _ = ctm.grad_tensor(ctx, a, 8, 10)
+    lk3, ex3, ga3, _ = ctm.grad_tensor(ctx, torch.tensor(a, device="cuda"), 8, 10)
+    assert ga3.is_cuda and lk3 == lk and np.array_equal(ga3.cpu().numpy(), ga)
+    # a host array passed as a device one is refused before anything runs
+    o = ctm.default_opts()
+    lkc, exc = ctypes.c_double(), ctypes.c_double()
+    info = ctm.ctm_grad_info()
+    gdev = torch.zeros_like(At)
+    rc = ctm.ctm_grad_purification_dev(ctx.h, ctypes.c_void_p(A.ctypes.data),
+                                       ctypes.c_void_p(Bt.data_ptr()), 3, 3, 2, 12, ctypes.byref(o),
+                                       2, 0, None, 0, 1.0, 0.0, ctypes.byref(lkc),
+                                       ctypes.byref(exc), ctypes.c_void_p(gdev.data_ptr()),
+                                       ctypes.c_void_p(gdev.data_ptr()), ctypes.byref(info))
+    assert rc == ctm.CTM_EINVAL and b"not device memory" in ctm.ctm_last_error(ctx.h)
+    assert not gdev.any()
+
