@@ -449,6 +449,23 @@ def run_xi(ctm, synth, reps):
     return out
 
 
+# per-mode figures: rates and times to 6 decimals; errors, changes and the
+# observables to 4 significant digits (rounding them to decimals would turn
+# a change of 1e-13 into 0)
+_SIGNIFICANT = ("err_kappa_vs_fp64", "err_energy_vs_fp64", "self_change_kappa", "self_change_energy",
+                "delta_last_sweep")
+
+
+def _fmt(k, v):
+    if not isinstance(v, float):
+        return v
+    if k in ("kappa", "energy_bond"):
+        return v
+    if k in _SIGNIFICANT:
+        return float("%.4g" % v)
+    return round(v, 6)
+
+
 def select_headline(runs, structured):
     """The headline mode: the fastest reduced-precision mode whose error
     against FP64 stays within a bound on both workloads, the tightest bound
@@ -568,10 +585,7 @@ def main():
         "fp64": {"value": round(ref["gflops"], 2), "ms_per_move": round(ref["ms_per_move"], 3),
                  "pct_fp64_mfma_peak_algorithmic": round(100.0 * ref["gflops"] / (PEAK_F64_TFLOPS * 1e3), 2),
                  "roofline": ref["roofline"]},
-        "modes": {MODE_NAMES[m]: {k: (round(v, 6) if isinstance(v, float) and k not in
-                                     ("err_kappa_vs_fp64", "err_energy_vs_fp64", "kappa", "energy_bond")
-                                     else v)
-                                  for k, v in r.items() if k != "roofline"}
+        "modes": {MODE_NAMES[m]: {k: _fmt(k, v) for k, v in r.items() if k != "roofline"}
                   for m, r in runs.items()},
         "roofline": h["roofline"],
         "fu_metric_ms": round(h["fu_ms"], 3),

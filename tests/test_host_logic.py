@@ -176,3 +176,13 @@ def test_per_move_table_is_the_difference_of_two_traces(tmp_path):
     assert float(lines["k1"][0]) == pytest.approx(2.0) and float(lines["k1"][1]) == pytest.approx(2.0)
     assert "setup" not in lines
     assert float(lines["total"][1]) == pytest.approx(5.0)
+
+
+def test_small_per_mode_figures_keep_their_digits():
+    """Errors and self-changes far below 1e-6 are reported to 4 significant
+    digits, not rounded to 0 by a fixed number of decimals."""
+    assert bench._fmt("self_change_kappa", 2.1e-13) == pytest.approx(2.1e-13)
+    assert bench._fmt("err_energy_vs_fp64", 2.716777e-09) == 2.717e-09
+    assert bench._fmt("ms_per_move", 3.45292412) == 3.452924
+    assert bench._fmt("kappa", 15.547744270432997) == 15.547744270432997
+    assert bench._fmt("launches", 120) == 120
