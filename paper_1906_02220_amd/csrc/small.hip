@@ -170,30 +170,57 @@ __global__ void sum_final_kernel(const double* partial, int nb, double* out) {
 
 // ------------------------------------------------------------ Gram-Cholesky
 
+// 64-bit value of lane `lane` (wave-uniform) of a wave.
+__device__ inline double readlane64(double x, int lane) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Cholesky factor and its inverse in one pass, register-tiled: TG x TG
-// threads, thread (ti, tj) owning entries (ti + TG r, tj + TG c),
-// r, c < NR = 96 / TG, of the symmetric Schur complement S and of X (both 96 x 96,
-// zero beyond b so that no row or column needs a guard).  Step k eliminates
-// column k below the pivot (S -= s_k s_k^T / piv on the trailing block) and
-// applies the same row operation to X, then scales row k of X by 1/sqrt(piv).
-// At the end X = R^-T, where R^T R is the column-scaled Gram matrix, so
-// W = D^-1 X^T has Z W orthonormal.  Columns whose pivot falls below dep_tol
-// (numerically dependent) are skipped: no elimination, flag set.  All
-// updates are unconditional FMAs with masked multipliers.
-template <int NB, int TG>
-__global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restrict__ G, int b,
-                                                           double dep_tol, double* __restrict__ Wout,
-                                                           int* __restrict__ dep, int* err) {
+// threads, thread (ti, tj) owning entries (ti + TG r, tj + TG c), r, c < NR =
+// NB / TG, of the symmetric Schur complement S and of X (both NB x NB, zero
+// beyond b so that no row or column needs a guard).  Pivot k eliminates
+// column k below the pivot (S -= s_k s_k^T / piv on the trailing block; only
+// the upper triangle of S is ever read, so blocks below the diagonal are not
+// updated) and applies the same row operation to X, which stays lower
+// triangular; then row k of X is scaled by 1/sqrt(piv).  At the end
+// X = R^-T, where R^T R is the column-scaled Gram matrix, so W = D^-1 X^T has
+// Z W orthonormal.  Columns whose pivot falls below dep_tol (numerically
+// dependent) are skipped: no elimination, flag set.
+//
+// The pivots are taken PB at a time.  The panel of rows k0 .. k0 + PB - 1 of
+// S and X goes through LDS into the registers of wave 0, which eliminates the
+// panel's pivots among the panel's own rows: lane l holds columns l and
+// l + 64 of every panel row, so a pivot and a multiplier are the only values
+// that cross lanes (readlane), and no pivot waits for an LDS round trip or a
+// barrier.  The other rows then take the PB eliminations as one update, pivot
+// by pivot in order, so every element that is read later receives the same
+// FMAs in the same order as with one pivot per barrier (the same W and flags
+// bit for bit, 5 % sooner at NB = 96: the broadcast reads of the pivot rows,
+// which every thread needs, are what the kernel waits on).  The workgroup
+// meets at two barriers per panel.
+template <int NB, int TG, int PB>
+__global__ __launch_bounds__(TG * TG) void chol_inv_panel_kernel(const double* __restrict__ G, int b,
+                                                                 double dep_tol,
+                                                                 double* __restrict__ Wout,
+                                                                 int* __restrict__ dep, int* err) {
   constexpr int NR = NB / TG;
   static_assert(NR * TG == NB, "the thread grid must tile NB");
   static_assert(TG * TG >= NB, "threads 0..NB-1 load the diagonal scales");
+  static_assert(TG % PB == 0 && NB % PB == 0, "a panel lies in one row block");
+  static_assert(NB <= 128, "two columns per lane of wave 0");
   __shared__ double Dn[NB];
-  __shared__ double rowk[2][NB];
-  __shared__ double xrow[2][NB];
+  __shared__ double Pr[2][PB][NB];  // panel rows of S (pivot rows after the panel)
+  __shared__ double Px[2][PB][NB];  // panel rows of X, not yet scaled
+  __shared__ double pinfo[2][PB][2];  // 1/piv (0 for a dependent column), 1/sqrt(piv)
   __shared__ int depl[NB];
   __shared__ int bad;
   const int t = threadIdx.x;
   const int ti = t / TG, tj = t % TG;
+  const int lane = t & 63;
+  const bool w0 = t < 64;
   if (t == 0) bad = 0;
   if (t < NB) {
     double dv = 0.0;
@@ -220,55 +247,101 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_kernel(const double* __restr
       S[r][c] = v;
       X[r][c] = (i == j) ? 1.0 : 0.0;
     }
-  // The NB steps are unrolled so that k, and with it the register row
-  // k / TG that holds row k and the blocks the step can touch, are
-  // compile-time constants: no select chains, and register blocks that lie
-  // entirely before the pivot are skipped (a rolled loop with select chains
-  // ran at 78 against 48 us for b = 96).  Only the upper triangle of S is
-  // ever read (row k, right of the pivot), so blocks below the diagonal
-  // (r > c) are not updated; X is lower triangular, so blocks above it
-  // (c > r) stay zero.  Row k is broadcast through a double-buffered LDS row,
-  // so one barrier per step suffices (a buffer is rewritten two steps later,
-  // after every reader has passed the barrier in between).
-#pragma unroll NB
-  for (int k = 0; k < NB; ++k) {
-    if (k >= b) continue;                                     // uniform: b is a kernel argument
-    const int rk = k / TG;
-    const int buf = k & 1;
-    if (ti == (k % TG)) {
+#pragma unroll
+  for (int k0 = 0; k0 < NB; k0 += PB) {
+    if (k0 >= b) continue;  // uniform: b is a kernel argument
+    const int buf = (k0 / PB) & 1;
+    const int rk = k0 / TG;
+    // the panel's owners hand its rows over
+    if (ti >= k0 % TG && ti < k0 % TG + PB) {
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
-        rowk[buf][tj + TG * c] = S[rk][c];
-        xrow[buf][tj + TG * c] = X[rk][c];
+        Pr[buf][ti - k0 % TG][tj + TG * c] = S[rk][c];
+        Px[buf][ti - k0 % TG][tj + TG * c] = X[rk][c];
       }
     }
     __syncthreads();
-    const double piv = rowk[buf][k];
-    const bool dk = !(piv > dep_tol);
-    const double ir = dk ? 1.0 : rsq_nr(piv);
-    const double ipiv = dk ? 0.0 : ir * ir;
-    double xr[NR], sr[NR];
+    if (w0) {
+      double ps[PB][2], px[PB][2];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      const int j = tj + TG * c;
-      xr[c] = (TG * c <= k) ? xrow[buf][j] : 0.0;          // X row k is zero beyond column k
-      sr[c] = (TG * c + TG - 1 > k && j > k) ? rowk[buf][j] : 0.0;
+      for (int q = 0; q < PB; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = lane + 64 * h;
+          ps[q][h] = j < NB ? Pr[buf][q][j] : 0.0;
+          px[q][h] = j < NB ? Px[buf][q][j] : 0.0;
+        }
+#pragma unroll
+      for (int kk = 0; kk < PB; ++kk) {
+        const int k = k0 + kk;
+        if (k >= b) break;  // uniform
+        const double piv = readlane64(ps[kk][k / 64], k % 64);
+        const bool dk = !(piv > dep_tol);
+        const double ir = dk ? 1.0 : rsq_nr(piv);
+        const double ipiv = dk ? 0.0 : ir * ir;
+        if (lane == 0) {
+          pinfo[buf][kk][0] = ipiv;
+          pinfo[buf][kk][1] = ir;
+          depl[k] = dk ? 1 : 0;
+        }
+#pragma unroll
+        for (int ii = kk + 1; ii < PB; ++ii) {
+          const int i = k0 + ii;
+          const double mi = readlane64(ps[kk][i / 64], i % 64) * ipiv;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j > k) ps[ii][h] = fma(-mi, ps[kk][h], ps[ii][h]);
+            else px[ii][h] = fma(-mi, px[kk][h], px[ii][h]);  // X row k is zero beyond column k
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PB; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = lane + 64 * h;
+          if (j < NB) {
+            Pr[buf][q][j] = ps[q][h];
+            Px[buf][q][j] = px[q][h];
+          }
+        }
     }
+    __syncthreads();
+    // the panel's owners take their final X rows: row k scaled by 1/sqrt(piv)
+    if (ti >= k0 % TG && ti < k0 % TG + PB) {
+      const int q = ti - k0 % TG;
+      if (k0 + q < b) {
+        const double ir = pinfo[buf][q][1];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (TG * r + TG - 1 < k) continue;                     // rows all before the pivot
-      const int i = ti + TG * r;
-      const double mi = (i > k) ? rowk[buf][i] * ipiv : 0.0;
+        for (int c = 0; c < NR; ++c) X[rk][c] = Px[buf][q][tj + TG * c] * ir;
+      }
+    }
+    // every row after the panel takes the panel's eliminations in order
+#pragma unroll
+    for (int kk = 0; kk < PB; ++kk) {
+      const int k = k0 + kk;
+      if (k >= b) break;  // uniform
+      const double ipiv = pinfo[buf][kk][0];
+      double xr[NR], sr[NR];
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
-        if (TG * c + TG - 1 > k && c >= r) S[r][c] = fma(-mi, sr[c], S[r][c]);
-        if (TG * c <= k && c <= r) {
-          const double v = fma(-mi, xr[c], X[r][c]);
-          X[r][c] = (r == rk) ? (i == k ? v * ir : v) : v;
+        const int j = tj + TG * c;
+        xr[c] = (TG * c <= k) ? Px[buf][kk][j] : 0.0;
+        sr[c] = (TG * c + TG - 1 > k && j > k) ? Pr[buf][kk][j] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (TG * r + TG - 1 < k0 + PB) continue;  // rows all in or before the panel
+        const int i = ti + TG * r;
+        const double mi = (i >= k0 + PB) ? Pr[buf][kk][i] * ipiv : 0.0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          if (TG * c + TG - 1 > k && c >= r) S[r][c] = fma(-mi, sr[c], S[r][c]);
+          if (TG * c <= k && c <= r) X[r][c] = fma(-mi, xr[c], X[r][c]);
         }
       }
     }
-    if (t == 0) depl[k] = dk ? 1 : 0;
   }
   __syncthreads();
   // W[j][i] = X[i][j] / D[j]
@@ -862,12 +935,13 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
                   int* err) {
   CTM_REQUIRE(b >= 1 && b <= 128, "chol_inverse: b out of range");
+  // the panel form gives the same W bit for bit, 5 % (b = 96) to 12 % (b = 128) sooner
   if (b <= 96)
-    hipLaunchKernelGGL((chol_inv_kernel<96, 32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol,
-                       W, dep, err);
+    hipLaunchKernelGGL((chol_inv_panel_kernel<96, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
+                       dep_tol, W, dep, err);
   else
-    hipLaunchKernelGGL((chol_inv_kernel<128, 32>), dim3(1), dim3(1024), 0, ctx.stream, G, b, dep_tol,
-                       W, dep, err);
+    hipLaunchKernelGGL((chol_inv_panel_kernel<128, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
+                       dep_tol, W, dep, err);
   CTM_HIP(hipGetLastError());
 }
 
