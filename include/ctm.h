@@ -78,8 +78,8 @@ typedef struct ctm_opts {
                              NULL: e_0 for ctm_env_init_tensor, vec(I_D) for
                              ctm_env_init_purification */
   int svd_oversample;     /* with svd_block = 0: b = min(chi*d, chi + svd_oversample,
-                             128); 0 = automatic, b = min(chi*d, max(96, chi + 24),
-                             128) */
+                             128); 0 = automatic, b = min(chi*d, 128,
+                             max(88, chi + max(16, ceil(chi / 4)))) */
   double svd_tol;         /* > 0: after each truncated SVD's fixed iterations, iterate
                              again from its vectors (at most 8 more times) until
                              max_i ||M u_i - s_i v_i|| / s_1 over the kept chi

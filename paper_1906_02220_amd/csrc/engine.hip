@@ -55,11 +55,14 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
     b = std::min(opt.svd_block, n);
   } else {
     // the chi kept directions plus a margin that separates them from the
-    // rest of the spectrum during the subspace iteration
-    // (an automatic 8 columns saved 6% of the move at D = 6, chi = 72 but
-    // lost the FP64 parity of nearly degenerate cut spectra: corner spectra
-    // 1e-5 off at D = 4, chi = 32)
-    b = opt.svd_oversample > 0 ? chi + opt.svd_oversample : std::max(96, chi + 24);
+    // rest of the spectrum during the subspace iteration: a quarter of chi,
+    // at least 16 columns, at least 88 in all.  Two sweeps from the start,
+    // FP64 stays within 1e-9 of the oracle's bond-metric entries at D = 6,
+    // chi = 72 with 16 columns (8 columns: 4e-8) and at D = 7, chi = 96 with
+    // 24 (16 columns: 1.7e-8); 8 columns also lost the FP64 parity of nearly
+    // degenerate cut spectra (corner spectra 1e-5 off at D = 4, chi = 32)
+    b = opt.svd_oversample > 0 ? chi + opt.svd_oversample
+                               : std::max(88, chi + std::max(16, (chi + 3) / 4));
     b = std::min(b, std::min(n, bmax));
   }
   if (opt.svd_iters <= 0) opt.svd_iters = 2;
