@@ -264,8 +264,11 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
     OutMap om) {
   constexpr int BM = 128, BN = 128, BK = 32;
   constexpr int TI = 2, TJ = 4;
-  __shared__ __attribute__((aligned(1024))) __bf16 As[2][S][BM * BK];
-  __shared__ __attribute__((aligned(1024))) __bf16 Bs[2][S][BN * BK];
+  // LDS stages: three at S = 3 (144 KB), loaded two K steps ahead; two at
+  // S = 4 (128 KB), one step ahead
+  constexpr int NS = S == 3 ? 3 : 2;
+  __shared__ __attribute__((aligned(1024))) __bf16 As[NS][S][BM * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 Bs[NS][S][BN * BK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
   int tm, tn;
@@ -290,11 +293,16 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
       load_to_lds16(bg + st * bstep + i * BK, b_lds + buf * stage_bytes + i * slice_bytes);
     }
   };
-  // every load of this wave has landed, every LDS read has returned, then all
-  // waves meet
-  auto step_barrier = [&]() {
-    __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  // the loads of the stage needed next have landed (a wave issues 2 S loads
+  // per stage and they complete in order, so vmcnt(2 S) leaves only the
+  // stage issued in this step in flight; vmcnt(0) when none was issued),
+  // every LDS read has returned, then all waves meet
+  constexpr int kVmStage = 0xF70 | (2 * S);  // s_waitcnt vmcnt(2 S)
+  static_assert(2 * S < 16, "vmcnt field");
+  auto step_barrier = [&](bool stage_in_flight) {
+    if (stage_in_flight) __builtin_amdgcn_s_waitcnt(kVmStage);
+    else __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+    __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0)
     asm volatile("s_barrier" ::: "memory");
   };
   f4 acc0[TI][TJ], accr[TI][TJ];
@@ -322,12 +330,15 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
       }
   };
   load(0, 0);
-  step_barrier();
+  if (NS == 3 && BK < Kp) load(BK, 1);
+  step_barrier(NS == 3 && BK < Kp);
   int buf = 0;
   for (int kt = 0; kt < Kp; kt += BK) {
     const bool more = kt + BK < Kp;
-    // the other stage was last read in the previous step, behind the barrier
-    if (more) load(kt + BK, buf ^ 1);
+    // the stage loaded here was last read NS - 1 steps ago, behind a barrier
+    const int ahead = (NS - 1) * BK;
+    const bool issue = kt + ahead < Kp;
+    if (issue) load(kt + ahead, buf + NS - 1 < NS ? buf + NS - 1 : buf - 1);
     bf8 a[TI][S];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -351,8 +362,8 @@ __global__ __launch_bounds__(512) void gemm_bf16s_kernel(
       }
     }
     if (((kt + BK) % kChunk) == 0 || !more) flush();
-    step_barrier();
-    buf ^= 1;
+    step_barrier(issue && NS == 3);
+    buf = buf + 1 < NS ? buf + 1 : 0;
   }
   // epilogue: C = acc 2^(eA + eB - 16), placed by om (the row and column
   // parts of the offset are computed once per row and per column)
