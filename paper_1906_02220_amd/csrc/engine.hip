@@ -19,6 +19,7 @@
 // The first three of these are the directional four-quadrant projectors of
 // the square-lattice CTMRG the paper builds on (Fig. 4(c)).
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -271,6 +272,15 @@ void Env::orth(double* Z, double* Q, int passes) {
   }
 }
 
+// Column norm (relative to the Frobenius norm) below which the Rayleigh-Ritz
+// Jacobi takes a column of its k x k matrix for zero: k eps, the rounding
+// level of its k-term dot products.  The adjoint's calls (svd_tol > 0)
+// converge every pair instead, and so does the full SVD of a small cut
+// matrix, which the adjoint shares with plain sweeps.
+static double jacobi_zero_level(const EnvOptions& o, int k) {
+  return o.svd_tol > 0.0 ? 0.0 : k * DBL_EPSILON;
+}
+
 // a6: top-chi singular triplets of M = Mt^T by subspace iteration on the
 // warm start of the previous move in the same direction.  Left vectors of
 // Mt (= Y of M) go to UA, right vectors (= X of M) to VA, values to sv;
@@ -330,12 +340,17 @@ void Env::subspace_iteration(const double* MtP) {
 
 // Rayleigh-Ritz on the subspace Om: Z = Mt Om = Qz B with B upper triangular,
 // B = x s y^T, so Mt Om = (Qz x) s y^T: UA = Qz x, VA = Om y, sv = s.
+//
+// Columns of B below b eps ||B||_F (a subspace wider than the numerical rank
+// of Mt) are zero to working precision and do not hold the Jacobi sweeps
+// open; the adjoint's calls (svd_tol > 0) converge every pair.
 void Env::rayleigh_ritz(const double* MtP) {
   int* err = (int*)iflags.p + 1;
   gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
   orth(Z0.d(), Qz.d(), 2);
   gemm_f64(ctx, b, b, n, 1.0, colmajor(Qz.d(), b), rowmajor(Z0.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
-  jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, true);
+  jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, true,
+             jacobi_zero_level(opt, b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
   fix_signs(ctx, UA.d(), b, VA.d(), b, n, b);

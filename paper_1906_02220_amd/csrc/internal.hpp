@@ -321,10 +321,13 @@ void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* d
 // when only the values are wanted; vectors are computed for one matrix per
 // call (batch = 1), values for batch matrices at stride bstride.  With
 // trans the rotations act on the columns of B^T (faster for a graded upper
-// triangular B).  *err = 1 if the sweeps did not converge or produced
-// non-finite values.
+// triangular B).  With zr > 0, pairs whose smaller column is at most
+// zr ||B||_F (zero to working precision for zr ~ b eps) do not keep the sweeps
+// going.  *err = 1 if the sweeps did not converge or produced non-finite
+// values.
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
-                int batch = 1, long long bstride = 0, long long sstride = 0, bool trans = false);
+                int batch = 1, long long bstride = 0, long long sstride = 0, bool trans = false,
+                double zr = 0.0);
 // Maximum b supported by jacobi_svd with vectors / values only.
 int jacobi_max_b(bool vectors);
 // out[i] = ||Y[:, i] - s[i] V[:, i]||_2 for i < kk (Y, V: n rows, leading

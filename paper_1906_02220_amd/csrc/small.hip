@@ -433,15 +433,20 @@ __device__ inline int jac_row(int i, int j) {
 // column's place in the descending order in rank_out, and
 // jacobi_replay_kernel rebuilds J from them.  On exit so holds the singular
 // values (the column norms of W) in descending order and Uo, if given, the
-// normalised columns of W in that order.  Sweeps stop after one whose largest
-// relative coupling |ga| / sqrt(al be) was below 1e-9: Jacobi converges
-// quadratically, so the couplings left are of order 1e-18, below the
-// rotation threshold b eps.
+// normalised columns of W in that order.  Sweeps stop after one in which no
+// rotation had a relative coupling |ga| / sqrt(al be) above 1e-9: Jacobi
+// converges quadratically, so the couplings left are of order 1e-18, below
+// the rotation threshold b eps.  With zr > 0 a pair whose smaller column has
+// a norm of at most zr ||A||_F does not keep the sweeps going: for zr at the
+// rounding level of A's entries such a column is zero to working precision,
+// its direction and its coupling with any other column carry no information,
+// and its relative coupling can stay large for many sweeps (the pair is still
+// rotated while above the rotation threshold).
 template <int RPT, int LPP>
 __global__ __launch_bounds__(1024) void jacobi_kernel(
     const double* __restrict__ Bm, int b, long long bstride, long long sstride,
     double* __restrict__ Uo, double* __restrict__ so, double2* __restrict__ rotlog,
-    int* __restrict__ rank_out, int* __restrict__ sweeps_out, int* err, int trans) {
+    int* __restrict__ rank_out, int* __restrict__ sweeps_out, int* err, int trans, double zr) {
   constexpr int ld = LPP * RPT;
   static_assert(RPT % (LPP == 16 ? 2 : 4) == 0, "the row-block exchange needs whole block pairs");
   extern __shared__ double lds[];
@@ -453,17 +458,26 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(
   __shared__ int changed;
   __shared__ int big;
   __shared__ int bad;
+  __shared__ double fro_part[16];
   const int t = threadIdx.x;
   const int nt = blockDim.x;
   const double* B = Bm + blockIdx.x * bstride;
   if (t == 0) { changed = 0; big = 0; bad = 0; }
+  double fro = 0.0;
   for (int idx = t; idx < bp * ld; idx += nt) {
     const int j = idx / ld, i = idx - (idx / ld) * ld;
     double v = 0.0;
     if (j < b && i < b) v = trans ? B[(long long)j * b + i] : B[(long long)i * b + j];
     Wc[j * ld + jac_row<LPP>(i, j)] = v;
+    fro = fma(v, v, fro);
   }
+  // ||A||_F^2 (rotations keep it): per wave, then over the waves
+  for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
+  if ((t & 63) == 0) fro_part[t >> 6] = fro;
   __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < (nt + 63) / 64; ++w) fro2 += fro_part[w];
+  const double zr2f2 = zr > 0.0 ? zr * zr * fro2 : 0.0;
   const int g = t / LPP;
   const int sub = t - g * LPP;
   const bool active = g < P;
@@ -530,7 +544,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(
           }
           if (sub == 0) {
             changed = 1;
-            if (ga * ga > 1e-18 * al * be) big = 1;
+            if (ga * ga > 1e-18 * al * be && fmin(al, be) > zr2f2) big = 1;
           }
         }
         if (rotlog && sub == 0) rotlog[((size_t)sweeps * m1 + r) * P + g] = make_double2(c, s);
@@ -878,8 +892,9 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
 int jacobi_max_b(bool) { return kJacobiMaxB; }
 
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
-                int batch, long long bstride, long long sstride, bool trans) {
+                int batch, long long bstride, long long sstride, bool trans, double zr) {
   CTM_REQUIRE(b >= 1 && b <= kJacobiMaxB, "jacobi_svd: b out of range");
+  CTM_REQUIRE(zr >= 0.0 && zr < 1.0, "jacobi_svd: zr out of range");
   double* Uo = trans ? Y : X;  // normalised columns of the working matrix
   double* Vo = trans ? X : Y;  // accumulated rotations
   CTM_REQUIRE(Vo == nullptr || batch == 1, "jacobi_svd: rotations of one matrix at a time");
@@ -914,7 +929,7 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
   do {                                                                                            \
     allow_lds((const void*)jacobi_kernel<R, LPP>, lds);                                           \
     hipLaunchKernelGGL((jacobi_kernel<R, LPP>), dim3(batch), dim3(threads), lds, ctx.stream, B, b, \
-                       bstride, sstride, Uo, s, rotlog, rank, sweeps, err, trans ? 1 : 0);        \
+                       bstride, sstride, Uo, s, rotlog, rank, sweeps, err, trans ? 1 : 0, zr);    \
   } while (0)
   if (rpt == 2) CTM_JAC(2);
   else if (rpt == 4) CTM_JAC(4);
