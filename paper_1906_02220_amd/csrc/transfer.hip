@@ -174,8 +174,8 @@ __global__ void arnoldi_step_kernel(double* H, int ldh, int j, const double* h1,
 // stride ld) of the Krylov basis, in two kernels each reading V once.
 // Projection: block b writes part[b * 64 + i] = sum over its chunk of
 // V[i][t] w[t] for every row at once (one accumulator per row, one
-// reduction per block); gs_sum_kernel adds the blocks' parts in block order
-// (a fixed order: the result does not depend on scheduling).
+// reduction per block); gs_sum_kernel adds the blocks' parts in a fixed
+// order (the result does not depend on scheduling).
 constexpr int kGsMaxRows = 64;
 __global__ __launch_bounds__(256) void gs_project_kernel(const double* __restrict__ V, size_t ld,
                                                          size_t dim, int rows,
@@ -209,27 +209,40 @@ __global__ __launch_bounds__(256) void gs_project_kernel(const double* __restric
     part[(size_t)blockIdx.x * kGsMaxRows + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
-// h[i] = sum over the blocks b of part[b * 64 + i]: four threads per row take
-// every fourth block with four independent accumulators, then the sixteen
-// partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void gs_sum_kernel(const double* __restrict__ part, int nblk,
-                                                     int rows, double* __restrict__ h) {
-  __shared__ double sh[4][kGsMaxRows];
+// h[i] = sum over the nblk blocks' parts of row i, one workgroup of
+// kGsSumGroups groups of 64 threads (one thread per row): group q adds parts
+// q, q + G, q + 2 G, ... in batches of kGsSumBatch loads in flight, into four
+// running sums, and the groups' sums then meet in a fixed tree, so the result
+// does not depend on scheduling.  (A serial chain of dependent loads took
+// 43 us per call.)
+constexpr int kGsSumGroups = 16;
+constexpr int kGsSumBatch = 8;
+__global__ __launch_bounds__(64 * kGsSumGroups) void gs_sum_kernel(const double* __restrict__ part,
+                                                                  int nblk, int rows,
+                                                                  double* __restrict__ h) {
+  __shared__ double sh[kGsSumGroups][kGsMaxRows];
   const int i = threadIdx.x & (kGsMaxRows - 1), q = threadIdx.x >> 6;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < rows) {
-    int b = q;
-    for (; b + 12 < nblk; b += 16) {
-      s0 += part[(size_t)b * kGsMaxRows + i];
-      s1 += part[(size_t)(b + 4) * kGsMaxRows + i];
-      s2 += part[(size_t)(b + 8) * kGsMaxRows + i];
-      s3 += part[(size_t)(b + 12) * kGsMaxRows + i];
+    constexpr int G = kGsSumGroups;
+    for (int b0 = q; b0 < nblk; b0 += G * kGsSumBatch) {
+      double v[kGsSumBatch];
+#pragma unroll
+      for (int u = 0; u < kGsSumBatch; ++u) {
+        const int b = b0 + u * G;
+        v[u] = b < nblk ? part[(size_t)b * kGsMaxRows + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kGsSumBatch; ++u) s[u & 3] += v[u];
     }
-    for (; b < nblk; b += 4) s0 += part[(size_t)b * kGsMaxRows + i];
   }
-  sh[q][i] = (s0 + s1) + (s2 + s3);
+  sh[q][i] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
-  if (q == 0 && i < rows) h[i] = (sh[0][i] + sh[1][i]) + (sh[2][i] + sh[3][i]);
+  for (int w = kGsSumGroups / 2; w > 0; w >>= 1) {
+    if (q < w) sh[q][i] += sh[q + w][i];
+    __syncthreads();
+  }
+  if (q == 0 && i < rows) h[i] = sh[0][i];
 }
 
 // w[t] -= sum_i V[i][t] h[i] for i < rows.
@@ -350,8 +363,8 @@ int Transfer::spectrum(int krylov, unsigned long long seed, double* wr_out, doub
       double* hp = pass == 0 ? h1 : h2;
       hipLaunchKernelGGL(gs_project_kernel, dim3(gblk), dim3(256), 0, ctx.stream, V.d(), dim, dim,
                          j + 1, w, part.d());
-      hipLaunchKernelGGL(gs_sum_kernel, dim3(1), dim3(256), 0, ctx.stream, part.d(), gblk, j + 1,
-                         hp);
+      hipLaunchKernelGGL(gs_sum_kernel, dim3(1), dim3(64 * kGsSumGroups), 0, ctx.stream, part.d(),
+                         gblk, j + 1, hp);
       hipLaunchKernelGGL(gs_update_kernel, dim3(nblk(dim)), dim3(256), 0, ctx.stream, V.d(), dim,
                          dim, j + 1, hp, w);
     }
