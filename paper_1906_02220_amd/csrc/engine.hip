@@ -262,7 +262,12 @@ void Env::orth(double* Z, double* Q, int passes) {
     double* dst = (pass == passes - 1) ? Q : ((pass & 1) ? Zb.d() : Wv.d());
     if (dst == src) dst = (src == Wv.d()) ? Zb.d() : Wv.d();
     gemm_f64(ctx, b, b, n, 1.0, colmajor(src, b), rowmajor(src, b), 0.0, out_rowmajor(G.d(), b));
-    chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err);
+    // A second pass usually starts from columns that the first left
+    // orthonormal to rounding; the first-order correction (3 I - G) / 2 then
+    // replaces the one-workgroup Cholesky inverse, which still runs when the
+    // first pass refilled dependent columns or left more than 1e-10 (decided
+    // on the device).
+    chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err, pass > 0 ? (int*)iflags.p + 2 : nullptr);
     gemm_f64(ctx, n, b, b, 1.0, rowmajor(src, b), rowmajor(Wm.d(), b), 0.0, out_rowmajor(dst, b));
     unsigned long long* rc = (unsigned long long*)rngc.p;
     refill_columns(ctx, dst, b, n, b, dep, opt.seed ^ 0x5deece66dULL, rc + rng_slot,

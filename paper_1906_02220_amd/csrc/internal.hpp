@@ -301,13 +301,18 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
 // generator (SplitMix64 mixing of seed and element counter, Box-Muller).
 void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
                  unsigned long long counter);
-// From the b x b Gram matrix G = Z^T Z of an n x b block Z (b <= 96):
+// From the b x b Gram matrix G = Z^T Z of an n x b block Z (b <= 128):
 // W = D^-1 R^-1 with D = sqrt(diag G) and R^T R = D^-1 G D^-1 (upper R), so
 // that Z W has orthonormal columns.  A column whose Schur-complement pivot
 // falls below dep_tol is dependent: it takes no part in the elimination and
 // dep[j] = 1 (its column of Z W must be replaced).  *err = 1 on non-finite G.
+// With skip (one device int, for the second pass of a CholeskyQR): when
+// max |G - I| <= kNearIdentityTol, W = (3 I - G) / 2 instead (Z W is then
+// orthonormal to O(|G - I|^2)), no column is dependent, and the Cholesky
+// inverse is skipped on the device; *skip tells which path ran.
+constexpr double kNearIdentityTol = 1e-10;
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                  int* err);
+                  int* err, int* skip = nullptr);
 // Replace the columns j with dep[j] != 0 of an n x b row-major Q by standard
 // normal numbers from the counter-based generator, starting at the counter
 // *counter_in (device memory); *counter_out (another device slot) receives

@@ -178,6 +178,46 @@ __device__ inline double readlane64(double x, int lane) {
   return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// Second pass of a CholeskyQR: for the Gram matrix G = Q^T Q of columns that
+// the first pass left orthonormal up to E = G - I with max |E_ij| <= tau,
+// W = (3 I - G) / 2 = I - E / 2 makes Q W orthonormal up to W G W - I =
+// -(3/4) E^2 + O(E^3) (one step of the Newton-Schulz iteration for the polar
+// factor), with no dependent column: W and dep are written and *skip = 1, so
+// that chol_inv_panel_kernel leaves them alone.  Otherwise (a larger or
+// non-finite E, e.g. after refilled columns) *skip = 0 and the Cholesky
+// inverse runs as usual.  One workgroup.
+__global__ __launch_bounds__(1024) void near_identity_inverse_kernel(const double* __restrict__ G,
+                                                                     int b, double tau,
+                                                                     double* __restrict__ Wout,
+                                                                     int* __restrict__ dep,
+                                                                     int* __restrict__ skip) {
+  __shared__ double red[16];
+  __shared__ int ok;
+  const int t = threadIdx.x, nt = blockDim.x;
+  double e = 0.0;
+  for (int idx = t; idx < b * b; idx += nt) {
+    const int i = idx / b, j = idx - (idx / b) * b;
+    const double g = G[idx] - (i == j ? 1.0 : 0.0);
+    e = (g == g) ? fmax(e, fabs(g)) : INFINITY;  // fmax would drop a NaN
+  }
+  for (int o = 32; o > 0; o >>= 1) e = fmax(e, __shfl_xor(e, o));
+  if ((t & 63) == 0) red[t >> 6] = e;
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (nt + 63) / 64; ++w) m = fmax(m, red[w]);
+    ok = m <= tau;
+    *skip = ok;
+  }
+  __syncthreads();
+  if (!ok) return;
+  for (int idx = t; idx < b * b; idx += nt) {
+    const int i = idx / b, j = idx - (idx / b) * b;
+    Wout[idx] = (i == j ? 1.5 : 0.0) - 0.5 * G[idx];
+  }
+  for (int j = t; j < b; j += nt) dep[j] = 0;
+}
+
 // Cholesky factor and its inverse in one pass, register-tiled: TG x TG
 // threads, thread (ti, tj) owning entries (ti + TG r, tj + TG c), r, c < NR =
 // NB / TG, of the symmetric Schur complement S and of X (both NB x NB, zero
@@ -205,7 +245,9 @@ template <int NB, int TG, int PB>
 __global__ __launch_bounds__(TG * TG) void chol_inv_panel_kernel(const double* __restrict__ G, int b,
                                                                  double dep_tol,
                                                                  double* __restrict__ Wout,
-                                                                 int* __restrict__ dep, int* err) {
+                                                                 int* __restrict__ dep, int* err,
+                                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;  // near_identity_inverse_kernel wrote W (uniform exit)
   constexpr int NR = NB / TG;
   static_assert(NR * TG == NB, "the thread grid must tile NB");
   static_assert(TG * TG >= NB, "threads 0..NB-1 load the diagonal scales");
@@ -948,15 +990,20 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
 }
 
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                  int* err) {
+                  int* err, int* skip) {
   CTM_REQUIRE(b >= 1 && b <= 128, "chol_inverse: b out of range");
+  if (skip) {
+    hipLaunchKernelGGL(near_identity_inverse_kernel, dim3(1), dim3(1024), 0, ctx.stream, G, b,
+                       kNearIdentityTol, W, dep, skip);
+    CTM_HIP(hipGetLastError());
+  }
   // the panel form gives the same W bit for bit, 5 % (b = 96) to 12 % (b = 128) sooner
   if (b <= 96)
     hipLaunchKernelGGL((chol_inv_panel_kernel<96, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
-                       dep_tol, W, dep, err);
+                       dep_tol, W, dep, err, skip);
   else
     hipLaunchKernelGGL((chol_inv_panel_kernel<128, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
-                       dep_tol, W, dep, err);
+                       dep_tol, W, dep, err, skip);
   CTM_HIP(hipGetLastError());
 }
 
