@@ -405,11 +405,16 @@ __global__ void refill_kernel(double* Q, int ldq, int n, int b, const int* __res
                               const unsigned long long* __restrict__ ctr_in,
                               unsigned long long* __restrict__ ctr_out) {
   __shared__ int dl[128];
-  for (int j = threadIdx.x; j < b; j += blockDim.x) dl[j] = dep[j];
+  int mine = 0;
+  for (int j = threadIdx.x; j < b; j += blockDim.x) {
+    dl[j] = dep[j];
+    mine |= dep[j];
+  }
   const unsigned long long ctr = *ctr_in;
   // the next call reads the other slot, so no block can see this write early
   if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = ctr + (unsigned long long)n * b;
-  __syncthreads();
+  // most calls have no dependent column: every block then leaves at once
+  if (!__syncthreads_or(mine)) return;
   const long long total = (long long)n * b;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
