@@ -61,32 +61,42 @@ constexpr int kChunk = 128;  // K chunk of exact FP32 accumulation (BF16 path)
 // ------------------------------------------------------------ slicing
 
 // max |x| over each row r of the R x K view (element (r, k) at p[r rs + k]),
-// one workgroup per row; rows are 16-byte aligned (the dispatcher checks p
-// and an even rs).  It also clears zero_out[0..nzero) for the column maxima
-// that follow on the same stream.
-__global__ __launch_bounds__(256) void rowmax_contig_kernel(const double* __restrict__ p,
-                                                            long long rs, int K,
-                                                            double* __restrict__ mx,
-                                                            double* __restrict__ zero_out,
-                                                            int nzero) {
-  __shared__ double sh[4];
-  const int r = blockIdx.x, t = threadIdx.x;
-  for (int i = blockIdx.x * 256 + t; i < nzero; i += gridDim.x * 256) zero_out[i] = 0.0;
+// one wave per row and four rows per workgroup; rows are 16-byte aligned (the
+// dispatcher checks p and an even rs).  Each lane keeps eight 16-byte loads
+// in flight; a workgroup per row, with five loads per thread, streamed only
+// 4.3 TB/s.  A NaN wins, so the maximum does not depend on the order.  It
+// also clears zero_out[0..nzero) for the column maxima that follow on the
+// same stream.
+constexpr int kRowmaxRows = 4;
+__global__ __launch_bounds__(64 * kRowmaxRows) void rowmax_contig_kernel(
+    const double* __restrict__ p, long long rs, int R, int K, double* __restrict__ mx,
+    double* __restrict__ zero_out, int nzero) {
+  const int t = threadIdx.x, lane = t & 63;
+  for (int i = blockIdx.x * blockDim.x + t; i < nzero; i += gridDim.x * blockDim.x) zero_out[i] = 0.0;
+  const int r = blockIdx.x * kRowmaxRows + (t >> 6);
+  if (r >= R) return;  // whole waves; no barrier follows
   auto take = [](double m, double v) { return (v > m || v != v) ? v : m; };  // a NaN wins
   const double* row = p + r * rs;
   double m0 = 0.0, m1 = 0.0;
-  for (int k = 2 * t; k + 1 < K; k += 512) {
-    const d2v v = *(const d2v*)(row + k);
-    m0 = take(m0, fabs(v.x));
-    m1 = take(m1, fabs(v.y));
+  constexpr int kBatch = 8;
+  for (int k0 = 2 * lane; k0 + 1 < K; k0 += 128 * kBatch) {
+    d2v v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int k = k0 + 128 * u;
+      v[u] = k + 1 < K ? *(const d2v*)(row + k) : d2v{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      m0 = take(m0, fabs(v[u].x));
+      m1 = take(m1, fabs(v[u].y));
+    }
   }
-  if ((K & 1) && t == 0) m0 = take(m0, fabs(row[K - 1]));
+  if ((K & 1) && lane == 0) m0 = take(m0, fabs(row[K - 1]));
   double m = take(m0, m1);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = take(m, __shfl_xor(m, off, 64));
-  if ((t & 63) == 0) sh[t >> 6] = m;
-  __syncthreads();
-  if (t == 0) mx[r] = take(take(sh[0], sh[1]), take(sh[2], sh[3]));
+  if (lane == 0) mx[r] = m;
 }
 
 // max |x| over each column n of a K x N row-major matrix (row stride ld):
@@ -596,7 +606,8 @@ void run_bf16s(Context& ctx, int M, int N, int K, const double* A, long long lda
   }
   // maxima: rows of A (contiguous; that kernel also clears bmax when B is
   // sliced here), columns of B (atomic max over K slabs)
-  hipLaunchKernelGGL(rowmax_contig_kernel, dim3(M), dim3(256), 0, ctx.stream, A, lda, K, amax,
+  hipLaunchKernelGGL(rowmax_contig_kernel, dim3((M + kRowmaxRows - 1) / kRowmaxRows),
+                     dim3(64 * kRowmaxRows), 0, ctx.stream, A, lda, M, K, amax,
                      bmax, slice_b ? N : 0);
   const int kslab = 32;
   if (slice_b)

@@ -790,9 +790,19 @@ __global__ void fix_signs_kernel(double* X, int ldx, double* Y, int ldy, int n) 
   const int t = threadIdx.x;
   double best = -1.0;
   int bi = 0x7fffffff;
-  for (int i = t; i < n; i += blockDim.x) {
-    const double v = fabs(X[(long long)i * ldx + j]);
-    if (v > best) { best = v; bi = i; }
+  // eight strided loads in flight, then compared in row order (the first
+  // row of the largest |value| wins, as in a plain scan)
+  const int nt = blockDim.x;
+  for (int i0 = t; i0 < n; i0 += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * nt;
+      v[u] = i < n ? fabs(X[(long long)i * ldx + j]) : -1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (v[u] > best) { best = v[u]; bi = i0 + u * nt; }
   }
   sv[t] = best;
   si[t] = bi;
