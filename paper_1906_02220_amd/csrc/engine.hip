@@ -267,7 +267,7 @@ void Env::orth(double* Z, double* Q, int passes) {
     // replaces the one-workgroup Cholesky inverse, which still runs when the
     // first pass refilled dependent columns or left more than 1e-10 (decided
     // on the device).
-    chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err, pass > 0 ? (int*)iflags.p + 2 : nullptr);
+    chol_inverse(ctx, G.d(), b, 1e-12, Wm.d(), dep, err, pass > 0);
     gemm_f64(ctx, n, b, b, 1.0, rowmajor(src, b), rowmajor(Wm.d(), b), 0.0, out_rowmajor(dst, b));
     unsigned long long* rc = (unsigned long long*)rngc.p;
     refill_columns(ctx, dst, b, n, b, dep, opt.seed ^ 0x5deece66dULL, rc + rng_slot,

@@ -148,7 +148,7 @@ class Env {
   DevBuf warm[4];
   bool warm_ok[4] = {false, false, false, false};
   DevBuf spec_s, spec_old, scal;  // scal: delta and observables scalars
-  DevBuf iflags;                  // [0] numeric, [1] svd, [2] second-pass skip, [8..] dependency flags
+  DevBuf iflags;                  // [0] numeric, [1] svd, [8..] dependency flags
   DevBuf E, E8;
   DevBuf resid;                   // column residuals of the truncated SVD, then s_1
   double* hres = nullptr;         // pinned host copy of resid

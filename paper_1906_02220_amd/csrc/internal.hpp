@@ -306,13 +306,13 @@ void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
 // that Z W has orthonormal columns.  A column whose Schur-complement pivot
 // falls below dep_tol is dependent: it takes no part in the elimination and
 // dep[j] = 1 (its column of Z W must be replaced).  *err = 1 on non-finite G.
-// With skip (one device int, for the second pass of a CholeskyQR): when
+// With first_order (for the second pass of a CholeskyQR): when
 // max |G - I| <= kNearIdentityTol, W = (3 I - G) / 2 instead (Z W is then
-// orthonormal to O(|G - I|^2)), no column is dependent, and the Cholesky
-// inverse is skipped on the device; *skip tells which path ran.
+// orthonormal to O(|G - I|^2)) and no column is dependent; the kernel decides
+// on the device and skips the factorisation.
 constexpr double kNearIdentityTol = 1e-10;
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                  int* err, int* skip = nullptr);
+                  int* err, bool first_order = false);
 // Replace the columns j with dep[j] != 0 of an n x b row-major Q by standard
 // normal numbers from the counter-based generator, starting at the counter
 // *counter_in (device memory); *counter_out (another device slot) receives

@@ -182,15 +182,12 @@ __device__ inline double readlane64(double x, int lane) {
 // the first pass left orthonormal up to E = G - I with max |E_ij| <= tau,
 // W = (3 I - G) / 2 = I - E / 2 makes Q W orthonormal up to W G W - I =
 // -(3/4) E^2 + O(E^3) (one step of the Newton-Schulz iteration for the polar
-// factor), with no dependent column: W and dep are written and *skip = 1, so
-// that chol_inv_panel_kernel leaves them alone.  Otherwise (a larger or
-// non-finite E, e.g. after refilled columns) *skip = 0 and the Cholesky
-// inverse runs as usual.  One workgroup.
-__global__ __launch_bounds__(1024) void near_identity_inverse_kernel(const double* __restrict__ G,
-                                                                     int b, double tau,
-                                                                     double* __restrict__ Wout,
-                                                                     int* __restrict__ dep,
-                                                                     int* __restrict__ skip) {
+// factor), with no dependent column.  Called by all threads of the Cholesky
+// kernel's workgroup: writes W and dep and returns true, or returns false
+// (a larger or non-finite E, e.g. after refilled columns) having written
+// nothing, and the Cholesky inverse runs as usual.
+__device__ bool near_identity_inverse(const double* __restrict__ G, int b, double tau,
+                                      double* __restrict__ Wout, int* __restrict__ dep) {
   __shared__ double red[16];
   __shared__ int ok;
   const int t = threadIdx.x, nt = blockDim.x;
@@ -207,15 +204,15 @@ __global__ __launch_bounds__(1024) void near_identity_inverse_kernel(const doubl
     double m = 0.0;
     for (int w = 0; w < (nt + 63) / 64; ++w) m = fmax(m, red[w]);
     ok = m <= tau;
-    *skip = ok;
   }
   __syncthreads();
-  if (!ok) return;
+  if (!ok) return false;
   for (int idx = t; idx < b * b; idx += nt) {
     const int i = idx / b, j = idx - (idx / b) * b;
     Wout[idx] = (i == j ? 1.5 : 0.0) - 0.5 * G[idx];
   }
   for (int j = t; j < b; j += nt) dep[j] = 0;
+  return true;
 }
 
 // Cholesky factor and its inverse in one pass, register-tiled: TG x TG
@@ -246,8 +243,9 @@ __global__ __launch_bounds__(TG * TG) void chol_inv_panel_kernel(const double* _
                                                                  double dep_tol,
                                                                  double* __restrict__ Wout,
                                                                  int* __restrict__ dep, int* err,
-                                                                 const int* __restrict__ skip) {
-  if (skip && *skip) return;  // near_identity_inverse_kernel wrote W (uniform exit)
+                                                                 double first_order_tol) {
+  // a second CholeskyQR pass near the identity needs no factorisation
+  if (first_order_tol > 0.0 && near_identity_inverse(G, b, first_order_tol, Wout, dep)) return;
   constexpr int NR = NB / TG;
   static_assert(NR * TG == NB, "the thread grid must tile NB");
   static_assert(TG * TG >= NB, "threads 0..NB-1 load the diagonal scales");
@@ -1005,20 +1003,16 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
 }
 
 void chol_inverse(Context& ctx, const double* G, int b, double dep_tol, double* W, int* dep,
-                  int* err, int* skip) {
+                  int* err, bool first_order) {
   CTM_REQUIRE(b >= 1 && b <= 128, "chol_inverse: b out of range");
-  if (skip) {
-    hipLaunchKernelGGL(near_identity_inverse_kernel, dim3(1), dim3(1024), 0, ctx.stream, G, b,
-                       kNearIdentityTol, W, dep, skip);
-    CTM_HIP(hipGetLastError());
-  }
+  const double fo = first_order ? kNearIdentityTol : 0.0;
   // the panel form gives the same W bit for bit, 5 % (b = 96) to 12 % (b = 128) sooner
   if (b <= 96)
     hipLaunchKernelGGL((chol_inv_panel_kernel<96, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
-                       dep_tol, W, dep, err, skip);
+                       dep_tol, W, dep, err, fo);
   else
     hipLaunchKernelGGL((chol_inv_panel_kernel<128, 32, 8>), dim3(1), dim3(1024), 0, ctx.stream, G, b,
-                       dep_tol, W, dep, err, skip);
+                       dep_tol, W, dep, err, fo);
   CTM_HIP(hipGetLastError());
 }
 
