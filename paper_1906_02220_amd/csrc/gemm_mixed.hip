@@ -205,21 +205,25 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
     }
   }
   __syncthreads();
-  // each thread: one row, 16 consecutive k (two 8-value groups)
-  const int rr = t >> 2, kq = (t & 3) * 16;
-  const int r = r0 + rr;
-  if (r >= R) return;
-  const int e = scale_exponent(mx[r]);
+  // each thread: 8 consecutive k of one row, for two rows; 8 lanes cover a
+  // row's 64 k, so each slice store writes whole 64-byte runs (a thread with
+  // 16 k wrote two separate 16-byte pieces of every run per store; the split
+  // went 3 % faster)
+  const int c8 = t & 7;
   const long long step = (long long)R * S * 32;
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int kb = k0 + kq + 8 * g;
-    if (kb >= Kp) break;
+  for (int h = 0; h < 2; ++h) {
+    const int rr = (t >> 3) + 32 * h;
+    const int r = r0 + rr;
+    if (r >= R) break;
+    const int kb = k0 + 8 * c8;
+    if (kb >= Kp) continue;
+    const int e = scale_exponent(mx[r]);
     __bf16 v[S][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       __bf16 o[S];
-      cut<S>(tile[rr][kq + 8 * g + u], e, o);
+      cut<S>(tile[rr][8 * c8 + u], e, o);
 #pragma unroll
       for (int i = 0; i < S; ++i) v[i][u] = o[i];
     }
