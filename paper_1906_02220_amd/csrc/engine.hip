@@ -349,6 +349,16 @@ void Env::subspace_iteration(const double* MtP) {
 // Columns of B below b eps ||B||_F (a subspace wider than the numerical rank
 // of Mt) are zero to working precision and do not hold the Jacobi sweeps
 // open; the adjoint's calls (svd_tol > 0) converge every pair.
+//
+// The Ritz vectors keep the signs the warm start carries through the Jacobi
+// rotations; no canonical sign is imposed.  Triplets on the near-degenerate
+// tail of the cut spectrum change by a few percent per move, so a rule such
+// as "largest entry positive" flips some of them from one move to the next.
+// Each flip changes the sign of an environment bond direction, the next cut
+// matrix then differs from the one the warm start was taken from by 1e-6 to
+// 1e-3 of s_1 along its leading directions, and about half of the warm
+// columns come out numerically dependent every move (they are refilled at
+// random, and the tail never converges).
 void Env::rayleigh_ritz(const double* MtP) {
   int* err = (int*)iflags.p + 1;
   gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
@@ -358,7 +368,6 @@ void Env::rayleigh_ritz(const double* MtP) {
              jacobi_zero_level(opt, b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
-  fix_signs(ctx, UA.d(), b, VA.d(), b, n, b);
 }
 
 // max_i ||Mt^T u_i - s_i v_i|| / s_1 over the kept i < min(chi, b), read back
