@@ -481,12 +481,14 @@ __device__ inline int jac_row(int i, int j) {
 // normalised columns of W in that order.  Sweeps stop after one in which no
 // rotation had a relative coupling |ga| / sqrt(al be) above 1e-9: Jacobi
 // converges quadratically, so the couplings left are of order 1e-18, below
-// the rotation threshold b eps.  With zr > 0 a pair whose smaller column has
-// a norm of at most zr ||A||_F does not keep the sweeps going: for zr at the
-// rounding level of A's entries such a column is zero to working precision,
-// its direction and its coupling with any other column carry no information,
-// and its relative coupling can stay large for many sweeps (the pair is still
-// rotated while above the rotation threshold).
+// the rotation threshold b eps.  With zr > 0 a pair whose two columns both
+// have a norm of at most zr ||A||_F does not keep the sweeps going: for zr at
+// the rounding level of A's entries such columns are zero to the precision
+// of A, their directions and their mutual coupling carry no information, and
+// their relative coupling can stay large for many sweeps (the pair is still
+// rotated while above the rotation threshold).  A pair with one larger column
+// still has to converge: its rotation angle can reach the ratio of the two
+// column norms, which for a column just above the level is not small.
 template <int RPT, int LPP>
 __global__ __launch_bounds__(1024) void jacobi_kernel(
     const double* __restrict__ Bm, int b, long long bstride, long long sstride,
@@ -589,7 +591,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(
           }
           if (sub == 0) {
             changed = 1;
-            if (ga * ga > 1e-18 * al * be && fmin(al, be) > zr2f2) big = 1;
+            if (ga * ga > 1e-18 * al * be && fmax(al, be) > zr2f2) big = 1;
           }
         }
         if (rotlog && sub == 0) rotlog[((size_t)sweeps * m1 + r) * P + g] = make_double2(c, s);
