@@ -280,20 +280,23 @@ void Env::orth(double* Z, double* Q, int passes) {
 
 // Column norm (relative to the Frobenius norm) below which the Rayleigh-Ritz
 // Jacobi takes a column of its k x k matrix for zero: k eps, the rounding
-// level of its k-term dot products, or, when the cut matrix comes from
-// reduced-precision products, the unit roundoff of their operands (2^-24 for
-// FP32 and three BF16 slices, 2^-32 for four).  Those products perturb the
-// cut matrix by about that fraction of its norm, which by Weyl's inequality
-// leaves singular values below it undetermined; rotating such columns into
-// each other only fits rounding noise.  The adjoint's calls (svd_tol > 0)
+// level of its k-term dot products.  The adjoint's calls (svd_tol > 0)
 // converge every pair instead, and so does the full SVD of a small cut
 // matrix, which the adjoint shares with plain sweeps.
 static double jacobi_zero_level(const EnvOptions& o, int k) {
-  if (o.svd_tol > 0.0) return 0.0;
-  const double u = o.precision == CTM_PREC_F64      ? 0.0
-                   : o.precision == CTM_PREC_BF16X4 ? 0x1p-32
-                                                    : 0x1p-24;
-  return std::max(k * DBL_EPSILON, u);
+  return o.svd_tol > 0.0 ? 0.0 : k * DBL_EPSILON;
+}
+
+// Relative accuracy of the cut matrix when it comes from reduced-precision
+// products: the unit roundoff of their operands, 2^-24 for FP32 and three BF16
+// slices, 2^-32 for four.  Those products perturb the cut matrix by about that
+// fraction of its norm, which by Weyl's inequality leaves its singular values
+// below that level undetermined; rotations between two such columns of B only
+// fit rounding noise and do not hold the Jacobi sweeps open.  FP64 and the
+// adjoint's calls return 0.
+static double jacobi_noise_level(const EnvOptions& o) {
+  if (o.svd_tol > 0.0 || o.precision == CTM_PREC_F64) return 0.0;
+  return o.precision == CTM_PREC_BF16X4 ? 0x1p-32 : 0x1p-24;
 }
 
 // a6: top-chi singular triplets of M = Mt^T by subspace iteration on the
@@ -356,10 +359,11 @@ void Env::subspace_iteration(const double* MtP) {
 // Rayleigh-Ritz on the subspace Om: Z = Mt Om = Qz B with B upper triangular,
 // B = x s y^T, so Mt Om = (Qz x) s y^T: UA = Qz x, VA = Om y, sv = s.
 //
-// Columns of B below the zero level of jacobi_zero_level times ||B||_F (a
-// subspace wider than the numerical rank of Mt) are zero to the precision of
-// Mt, and pairs of two such columns do not hold the Jacobi sweeps open; the
-// adjoint's calls (svd_tol > 0) converge every pair.
+// Columns of B below b eps ||B||_F (a subspace wider than the numerical rank
+// of Mt) are zero to working precision and do not hold the Jacobi sweeps
+// open, and neither do pairs of two columns below the accuracy of a
+// reduced-precision Mt; the adjoint's calls (svd_tol > 0) converge every
+// pair.
 //
 // The Ritz vectors keep the signs the warm start carries through the Jacobi
 // rotations; no canonical sign is imposed.  Triplets on the near-degenerate
@@ -376,7 +380,7 @@ void Env::rayleigh_ritz(const double* MtP) {
   orth(Z0.d(), Qz.d(), 2);
   gemm_f64(ctx, b, b, n, 1.0, colmajor(Qz.d(), b), rowmajor(Z0.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
   jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, true,
-             jacobi_zero_level(opt, b));
+             jacobi_zero_level(opt, b), jacobi_noise_level(opt));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
 }

@@ -326,14 +326,14 @@ void refill_columns(Context& ctx, double* Q, int ldq, int n, int b, const int* d
 // when only the values are wanted; vectors are computed for one matrix per
 // call (batch = 1), values for batch matrices at stride bstride.  With
 // trans the rotations act on the columns of B^T (faster for a graded upper
-// triangular B).  With zr > 0, pairs whose two columns are both at most
-// zr ||B||_F (zero to the precision of B) do not keep the sweeps going; a pair
-// with one larger column still does, since its rotation angle can reach the
-// ratio of the two column norms.  *err = 1 if the sweeps did not converge or
-// produced non-finite values.
+// triangular B).  With zr > 0, pairs with a column of norm at most
+// zr ||B||_F (zero to working precision for zr ~ b eps) do not keep the
+// sweeps going; with zp > 0, neither do pairs whose two columns are both at
+// most zp ||B||_F (B known to a relative accuracy zp).  *err = 1 if the
+// sweeps did not converge or produced non-finite values.
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
                 int batch = 1, long long bstride = 0, long long sstride = 0, bool trans = false,
-                double zr = 0.0);
+                double zr = 0.0, double zp = 0.0);
 // Maximum b supported by jacobi_svd with vectors / values only.
 int jacobi_max_b(bool vectors);
 // out[i] = ||Y[:, i] - s[i] V[:, i]||_2 for i < kk (Y, V: n rows, leading

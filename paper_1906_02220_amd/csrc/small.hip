@@ -481,19 +481,24 @@ __device__ inline int jac_row(int i, int j) {
 // normalised columns of W in that order.  Sweeps stop after one in which no
 // rotation had a relative coupling |ga| / sqrt(al be) above 1e-9: Jacobi
 // converges quadratically, so the couplings left are of order 1e-18, below
-// the rotation threshold b eps.  With zr > 0 a pair whose two columns both
-// have a norm of at most zr ||A||_F does not keep the sweeps going: for zr at
-// the rounding level of A's entries such columns are zero to the precision
-// of A, their directions and their mutual coupling carry no information, and
-// their relative coupling can stay large for many sweeps (the pair is still
-// rotated while above the rotation threshold).  A pair with one larger column
-// still has to converge: its rotation angle can reach the ratio of the two
-// column norms, which for a column just above the level is not small.
+// the rotation threshold b eps.  Two levels (relative to ||A||_F) exempt
+// pairs from keeping the sweeps going; an exempt pair is still rotated while
+// above the rotation threshold.
+//  * zr > 0: a pair with a column of norm at most zr ||A||_F.  At the rounding
+//    level of A's entries (zr ~ b eps) such a column is zero to working
+//    precision: its direction carries no information and its relative
+//    coupling with any other column never settles.
+//  * zp > 0: a pair whose two columns both have a norm of at most zp ||A||_F,
+//    for A known only to a relative accuracy zp.  Their mutual rotations fit
+//    the error of A.  A pair with one larger column still converges: left
+//    unconverged, the smaller column keeps a component of the larger one's
+//    direction as large as their relative coupling.
 template <int RPT, int LPP>
 __global__ __launch_bounds__(1024) void jacobi_kernel(
     const double* __restrict__ Bm, int b, long long bstride, long long sstride,
     double* __restrict__ Uo, double* __restrict__ so, double2* __restrict__ rotlog,
-    int* __restrict__ rank_out, int* __restrict__ sweeps_out, int* err, int trans, double zr) {
+    int* __restrict__ rank_out, int* __restrict__ sweeps_out, int* err, int trans, double zr,
+    double zp) {
   constexpr int ld = LPP * RPT;
   static_assert(RPT % (LPP == 16 ? 2 : 4) == 0, "the row-block exchange needs whole block pairs");
   extern __shared__ double lds[];
@@ -525,6 +530,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(
   double fro2 = 0.0;
   for (int w = 0; w < (nt + 63) / 64; ++w) fro2 += fro_part[w];
   const double zr2f2 = zr > 0.0 ? zr * zr * fro2 : 0.0;
+  const double zp2f2 = zp > 0.0 ? zp * zp * fro2 : 0.0;
   const int g = t / LPP;
   const int sub = t - g * LPP;
   const bool active = g < P;
@@ -591,7 +597,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(
           }
           if (sub == 0) {
             changed = 1;
-            if (ga * ga > 1e-18 * al * be && fmax(al, be) > zr2f2) big = 1;
+            if (ga * ga > 1e-18 * al * be && fmin(al, be) > zr2f2 && fmax(al, be) > zp2f2)
+              big = 1;
           }
         }
         if (rotlog && sub == 0) rotlog[((size_t)sweeps * m1 + r) * P + g] = make_double2(c, s);
@@ -949,7 +956,8 @@ void dot(Context& ctx, const double* x, const double* y, size_t n, double* resul
 int jacobi_max_b(bool) { return kJacobiMaxB; }
 
 void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, double* Y, int* err,
-                int batch, long long bstride, long long sstride, bool trans, double zr) {
+                int batch, long long bstride, long long sstride, bool trans, double zr,
+                double zp) {
   CTM_REQUIRE(b >= 1 && b <= kJacobiMaxB, "jacobi_svd: b out of range");
   CTM_REQUIRE(zr >= 0.0 && zr < 1.0, "jacobi_svd: zr out of range");
   double* Uo = trans ? Y : X;  // normalised columns of the working matrix
@@ -986,7 +994,7 @@ void jacobi_svd(Context& ctx, const double* B, int b, double* X, double* s, doub
   do {                                                                                            \
     allow_lds((const void*)jacobi_kernel<R, LPP>, lds);                                           \
     hipLaunchKernelGGL((jacobi_kernel<R, LPP>), dim3(batch), dim3(threads), lds, ctx.stream, B, b, \
-                       bstride, sstride, Uo, s, rotlog, rank, sweeps, err, trans ? 1 : 0, zr);    \
+                       bstride, sstride, Uo, s, rotlog, rank, sweeps, err, trans ? 1 : 0, zr, zp);    \
   } while (0)
   if (rpt == 2) CTM_JAC(2);
   else if (rpt == 4) CTM_JAC(4);
