@@ -67,7 +67,7 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
                                : std::max(88, chi + std::max(16, (chi + 3) / 4));
     b = std::min(b, std::min(n, bmax));
   }
-  if (opt.svd_iters <= 0) opt.svd_iters = 2;
+  if (opt.svd_iters <= 0) opt.svd_iters = 1;
   if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 5;
   alloc();
   CTM_HIP(hipHostMalloc((void**)&hbox, 64, hipHostMallocDefault));
