@@ -326,8 +326,13 @@ void Env::svd_top(const double* MtP, int k) {
   // intermediate ones the orthogonality error of each pass accumulates over
   // the iterations (12 iterations from the boundary start at D = 6, chi = 72
   // then left kappa 8e-9 from the full SVD's instead of 1e-10).
-  for (int it = 0; it < iters; ++it) subspace_iteration(MtP);
-  rayleigh_ritz(MtP);
+  if (opt.svd_tol > 0.0) {
+    for (int it = 0; it < iters; ++it) subspace_iteration(MtP);
+    rayleigh_ritz(MtP);
+  } else {
+    for (int it = 0; it + 1 < iters; ++it) subspace_iteration(MtP);
+    final_iteration_ritz(MtP);
+  }
   ++svd_calls;
   svd_iterations += iters;
   if (opt.svd_tol > 0.0) {
@@ -380,6 +385,27 @@ void Env::rayleigh_ritz(const double* MtP) {
   orth(Z0.d(), Qz.d(), 2);
   gemm_f64(ctx, b, b, n, 1.0, colmajor(Qz.d(), b), rowmajor(Z0.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
   jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, true,
+             jacobi_zero_level(opt, b), jacobi_noise_level(opt));
+  gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
+  gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));
+}
+
+// The last subspace iteration with the Rayleigh-Ritz step folded in:
+// Qz = orth(Mt Om) (two passes, since Qz is the final left basis),
+// Y = Mt^T Qz, Om = orth(Y).  Then Qz^T Mt Om = Y^T Om = B exactly (Om spans
+// Y), and Mt^T Qz lying in the span of Om gives Qz Qz^T Mt = Qz B Om^T, so
+// B = x s y^T yields UA = Qz x, VA = Om y without the product Mt Om and the
+// orthogonalisation of rayleigh_ritz.  B = Y^T Om = R^T for Y = Om R is lower
+// triangular, so the rotations act on its columns (the rows of R), the same
+// side as rayleigh_ritz's transposed call on its upper triangular factor.
+void Env::final_iteration_ritz(const double* MtP) {
+  int* err = (int*)iflags.p + 1;
+  gemm_f64(ctx, n, b, n, 1.0, rowmajor(MtP, n), rowmajor(Om.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+  orth(Z0.d(), Qz.d(), 2);
+  gemm_f64(ctx, n, b, n, 1.0, colmajor(MtP, n), rowmajor(Qz.d(), b), 0.0, out_rowmajor(Z0.d(), b));
+  orth(Z0.d(), Om.d(), 2);
+  gemm_f64(ctx, b, b, n, 1.0, colmajor(Z0.d(), b), rowmajor(Om.d(), b), 0.0, out_rowmajor(Bsm.d(), b));
+  jacobi_svd(ctx, Bsm.d(), b, xs.d(), sv.d(), ys.d(), err, 1, 0, 0, false,
              jacobi_zero_level(opt, b), jacobi_noise_level(opt));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Qz.d(), b), rowmajor(xs.d(), b), 0.0, out_rowmajor(UA.d(), b));
   gemm_f64(ctx, n, b, b, 1.0, rowmajor(Om.d(), b), rowmajor(ys.d(), b), 0.0, out_rowmajor(VA.d(), b));

@@ -124,6 +124,7 @@ class Env {
   void svd_top(const double* Mt, int k);
   void subspace_iteration(const double* Mt);
   void rayleigh_ritz(const double* Mt);
+  void final_iteration_ritz(const double* Mt);
   double svd_residual(const double* Mt);
   void orth(double* Z, double* Q, int passes);
   void ring();
