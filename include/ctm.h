@@ -70,7 +70,8 @@ typedef struct ctm_opts {
                              A cut matrix with chi*d <= 128 rows gets a full
                              Jacobi SVD instead. */
   int svd_iters;          /* subspace iterations per move when warm-started;
-                             0 = automatic (1) */
+                             0 = automatic: 2 for the first 8 warm moves of
+                             each direction after a random start, then 1 */
   int svd_iters_cold;     /* iterations from a random start; 0 = automatic (5) */
   unsigned long long seed;/* seed of the counter-based generator for cold
                              starts; default 0x5eed */

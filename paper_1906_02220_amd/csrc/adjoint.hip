@@ -349,7 +349,10 @@ void Grad::save(Ckpt& c) {
   copy_dev(ctx, c.logs.d(), e.logs.d(), 8);
   for (int k = 0; k < 4; ++k) copy_dev(ctx, c.warm.d() + k * nb, e.warm[k].d(), nb);
   copy_dev(ctx, c.rng.d(), (const double*)e.rngc.p, 2);  // bit copy of two counters
-  for (int k = 0; k < 4; ++k) c.warm_ok[k] = e.warm_ok[k];
+  for (int k = 0; k < 4; ++k) {
+    c.warm_ok[k] = e.warm_ok[k];
+    c.warm_moves[k] = e.warm_moves[k];
+  }
   c.rng_slot = e.rng_slot;
   c.rng_ctr = e.rng_ctr;
 }
@@ -363,6 +366,7 @@ void Grad::restore(const Ckpt& c) {
   copy_dev(ctx, (double*)e.rngc.p, c.rng.d(), 2);
   for (int k = 0; k < 4; ++k) {
     e.warm_ok[k] = c.warm_ok[k];
+    e.warm_moves[k] = c.warm_moves[k];
     e.qvalid[k] = false;
   }
   e.rng_slot = c.rng_slot;

@@ -38,6 +38,7 @@ class Grad {
   struct Ckpt {
     DevBuf C, T, logs, warm, rng;
     bool warm_ok[4];
+    int warm_moves[4];
     int rng_slot;
     unsigned long long rng_ctr;
   };

@@ -67,6 +67,7 @@ Env::Env(Context& c, int d_, int chi_, const EnvOptions& o) : ctx(c), d(d_), chi
                                : std::max(88, chi + std::max(16, (chi + 3) / 4));
     b = std::min(b, std::min(n, bmax));
   }
+  svd_iters_auto = opt.svd_iters <= 0;
   if (opt.svd_iters <= 0) opt.svd_iters = 1;
   if (opt.svd_iters_cold <= 0) opt.svd_iters_cold = 5;
   alloc();
@@ -316,11 +317,19 @@ void Env::svd_top(const double* MtP, int k) {
   int iters = opt.svd_iters;
   if (warm_ok[k]) {
     copy_dev(ctx, Om.d(), warm[k].d(), (size_t)n * b);
+    // Automatic count: two iterations while the environment is still far
+    // from its fixed point and the cut matrix changes a lot between moves,
+    // one afterwards.  At D = 3, chi = 20 one iteration from the second
+    // sweep on left <H> 1.5e-10 from the exact-SVD result after 6 sweeps
+    // (two: 3e-12) and 1e-12 after 10.
+    if (svd_iters_auto && warm_moves[k] < kSettleWarmMoves) iters = 2;
+    if (warm_moves[k] < kSettleWarmMoves) ++warm_moves[k];
   } else {
     fill_normal(ctx, Z0.d(), (size_t)n * b, opt.seed, rng_ctr);
     rng_ctr += (unsigned long long)n * b;
     orth(Z0.d(), Om.d(), 2);
     iters = opt.svd_iters_cold;
+    warm_moves[k] = 0;
   }
   // Every right basis gets two CholeskyQR passes: with one pass on the
   // intermediate ones the orthogonality error of each pass accumulates over
@@ -612,8 +621,9 @@ void Env::sweep_tail_eager() {
   CTM_HIP(hipMemcpyAsync(hbox + 1, iflags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
 }
 
-// A sweep may be captured once every direction runs warm (so the host takes
-// the same branches on every sweep) and a warm sweep has already run eagerly
+// A sweep may be captured once every direction runs warm with its final
+// iteration count (so the host takes the same branches on every sweep) and a
+// warm sweep has already run eagerly
 // (so every workspace the sweep needs exists and no allocation can fall into
 // the capture).  Timing events are not captured.
 bool Env::graph_ready() const {
@@ -621,7 +631,7 @@ bool Env::graph_ready() const {
   if (opt.svd_tol > 0.0) return false;  // its residual checks wait for the device
   if (n > jacobi_max_b(true))
     for (int k = 0; k < 4; ++k)
-      if (!warm_ok[k]) return false;
+      if (!warm_ok[k] || (svd_iters_auto && warm_moves[k] < kSettleWarmMoves)) return false;
   return true;
 }
 

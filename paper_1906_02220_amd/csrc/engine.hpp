@@ -148,6 +148,13 @@ class Env {
   DevBuf Om, Zb, Z0, Qz, Wv, G, Wm, Bsm, xs, ys, sv, UA, VA, winv, Pu, Pl, sm1, sm2, sm3;
   DevBuf warm[4];
   bool warm_ok[4] = {false, false, false, false};
+  // Warm moves per direction since its last cold start, counted up to
+  // kSettleWarmMoves.  With the automatic iteration count (svd_iters_auto)
+  // the first kSettleWarmMoves warm moves of a direction run two subspace
+  // iterations, later ones opt.svd_iters (one).
+  static constexpr int kSettleWarmMoves = 8;
+  int warm_moves[4] = {0, 0, 0, 0};
+  bool svd_iters_auto = false;
   DevBuf spec_s, spec_old, scal;  // scal: delta and observables scalars
   DevBuf iflags;                  // [0] numeric, [1] svd, [8..] dependency flags
   DevBuf E, E8;

@@ -46,11 +46,12 @@ def _same(s1, s2):
 def test_graph_replay_matches_eager_sweep_by_sweep():
     """D = 4, chi = 32 (subspace SVD with warm starts): every sweep replayed
     from the graph, with observables computed eagerly between replays,
-    equals the eager sweep."""
+    equals the eager sweep.  A fixed iteration count lets the graph be
+    captured from the third sweep on."""
     say("case: graph replay D=4 chi=32 seed=1234, 8 sweeps")
     ce, cg = ctm.Context(0), ctm.Context(0)
     cg.graphs(True)
-    ee, eg = _env(ce, 4, 32, 1234), _env(cg, 4, 32, 1234)
+    ee, eg = _env(ce, 4, 32, 1234, svd_iters=1), _env(cg, 4, 32, 1234, svd_iters=1)
     for s in range(8):
         r1, r2 = ee.sweep(1), eg.sweep(1)
         assert r1 == r2
@@ -62,6 +63,26 @@ def test_graph_replay_matches_eager_sweep_by_sweep():
     for s in range(4):
         assert ee.sweep(1) == eg.sweep(1)
         _same(_state(ee), _state(eg))
+    ce.close()
+    cg.close()
+
+
+def test_graph_replay_with_automatic_iteration_count():
+    """The automatic subspace iteration count runs two iterations for the
+    first eight warm moves of each direction and one afterwards; the graph is
+    captured only once the count has settled (from the tenth sweep on).
+    Sweep by sweep, 14 sweeps with graphs on equal the eager sweeps."""
+    say("case: graph replay D=4 chi=32 seed=99, automatic iteration count, 14 sweeps")
+    ce, cg = ctm.Context(0), ctm.Context(0)
+    cg.graphs(True)
+    ee, eg = _env(ce, 4, 32, 99), _env(cg, 4, 32, 99)
+    for s in range(14):
+        r1, r2 = ee.sweep(1), eg.sweep(1)
+        assert r1 == r2
+        _same(_state(ee), _state(eg))
+    calls, iters, _ = ee.svd_stats()
+    # 4 cold calls of 5 iterations, 32 warm calls of 2, the rest 1
+    assert calls == 56 and iters == 4 * 5 + 32 * 2 + 20 * 1
     ce.close()
     cg.close()
 
@@ -196,7 +217,7 @@ def test_grouped_batch_matches_sequential():
     ctxs = [ctm.Context(0) for _ in GROUPED[:-1]]
     ctxs.append(ctxs[0])
     ctxs[1].graphs(True)
-    batch = [_env(c, D, chi, seed, gamma, precision=p)
+    batch = [_env(c, D, chi, seed, gamma, precision=p, svd_iters=1)
              for c, (D, chi, seed, gamma, p) in zip(ctxs, GROUPED)]
     batch[1].sweep(3)  # captures a graph on the graph-enabled context
     rc, done, delta = ctm.sweep_batch(batch, 6, 0.0, grouped=True)
@@ -204,12 +225,12 @@ def test_grouped_batch_matches_sequential():
     cs = ctm.Context(0)
     for i, ((D, chi, seed, gamma, p), eb, db) in enumerate(zip(GROUPED, batch, delta)):
         say("  member %d: D=%d chi=%d precision %d" % (i, D, chi, p))
-        es = _env(cs, D, chi, seed, gamma, precision=p)
+        es = _env(cs, D, chi, seed, gamma, precision=p, svd_iters=1)
         _, _, dels = es.sweep(9 if i == 1 else 6)
         assert dels == db
         _same(_state(eb), _state(es))
     # graph replay resumes on the member whose graph was dropped
-    es = _env(cs, 4, 32, 7, 1, precision=ctm.CTM_PREC_F32)
+    es = _env(cs, 4, 32, 7, 1, precision=ctm.CTM_PREC_F32, svd_iters=1)
     es.sweep(9)
     assert batch[1].sweep(3) == es.sweep(3)
     _same(_state(batch[1]), _state(es))

@@ -87,7 +87,8 @@ def test_graphs_autotune_and_residual_control():
         c = ctm.Context(0)
         c.graphs(True)
         c.autotune(True)
-        e = ctm.Environment.from_purification(c, A, B, 2, 40, precision=ctm.CTM_PREC_BF16X3)
+        e = ctm.Environment.from_purification(c, A, B, 2, 40, precision=ctm.CTM_PREC_BF16X3,
+                                              svd_iters=1)
         e.sweep(4)
         out = _env_outputs(e)
         e.close()
