@@ -2,11 +2,15 @@
 //
 // When the innermost axis stays innermost, every thread copies one element
 // with both reads and writes contiguous along that axis.  Otherwise the
-// kernel transposes 32 x 32 tiles of the plane spanned by the input's
-// innermost axis (contiguous in the input) and the input axis that becomes
-// innermost in the output (contiguous in the output) through LDS, so both
-// the global reads and the global writes are coalesced; all remaining axes
-// enumerate the tiles' batch.
+// kernel transposes tiles of the plane spanned by the input's innermost axis
+// P (contiguous in the input) and the input axis Q that becomes innermost in
+// the output (contiguous in the output) through LDS, so both the global
+// reads and the global writes are coalesced; all remaining axes enumerate
+// the tiles' batch.  A tile spans the whole plane when it is small (P up to
+// 128, Q up to 64, at most kTileElems elements), so that planes such as the
+// 72 x 36 one of an edge tensor's [chi, d, d, chi] -> [chi, chi, d, d]
+// permutation move as one dense tile instead of six 32 x 32 tiles that are
+// 42 % full.
 #include "internal.hpp"
 
 namespace ctm {
@@ -44,11 +48,14 @@ struct TDesc {
   int nb;                // number of batch axes
   long long bdim[8], bin[8], bout[8];
   long long tilesP, tilesQ;
+  int TP, TQ;            // tile extent along P and Q
 };
+
+constexpr int kTileElems = 4096;  // LDS: TQ (TP + 1) doubles, at most 33 KB
 
 __global__ __launch_bounds__(256) void permute_tile_kernel(const double* __restrict__ in,
                                                            double* __restrict__ out, TDesc td) {
-  __shared__ double tile[32][33];
+  extern __shared__ double tile[];  // TQ rows of TP + 1 (odd row stride: no bank pile-up)
   const long long tilesPQ = td.tilesP * td.tilesQ;
   const long long bidx = blockIdx.x / tilesPQ;
   const long long trem = blockIdx.x - bidx * tilesPQ;
@@ -62,18 +69,24 @@ __global__ __launch_bounds__(256) void permute_tile_kernel(const double* __restr
     ooff += i * td.bout[a];
     rem = q;
   }
-  const long long p0 = tp * 32, q0 = tq * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-#pragma unroll
-  for (int r = 0; r < 32; r += 8) {
-    const long long q = q0 + ty + r, p = p0 + tx;
-    if (q < td.dimQ && p < td.dimP) tile[ty + r][tx] = in[ioff + q * td.qs_in + p];
+  const long long p0 = tp * td.TP, q0 = tq * td.TQ;
+  // extents of this tile (the last tile along an axis may be partial); the
+  // linear index runs over the np x nq elements only, so no thread idles on
+  // a partial tile
+  const int np = (int)min((long long)td.TP, td.dimP - p0);
+  const int nq = (int)min((long long)td.TQ, td.dimQ - q0);
+  const int ld = td.TP + 1;
+  const int cnt = np * nq;
+  // reads: runs of np consecutive P along each q
+  for (int idx = threadIdx.x; idx < cnt; idx += 256) {
+    const int q = idx / np, p = idx - q * np;
+    tile[q * ld + p] = in[ioff + (q0 + q) * td.qs_in + p0 + p];
   }
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 32; r += 8) {
-    const long long p = p0 + ty + r, q = q0 + tx;
-    if (q < td.dimQ && p < td.dimP) out[ooff + p * td.ps_out + q] = tile[tx][ty + r];
+  // writes: runs of nq consecutive Q along each p
+  for (int idx = threadIdx.x; idx < cnt; idx += 256) {
+    const int p = idx / nq, q = idx - p * nq;
+    out[ooff + (p0 + p) * td.ps_out + q0 + q] = tile[q * ld + p];
   }
 }
 
@@ -146,13 +159,18 @@ void permute(Context& ctx, const double* in, double* out, int rank, const long l
     td.bout[td.nb] = mo[a];
     ++td.nb;
   }
-  td.tilesP = (td.dimP + 31) / 32;
-  td.tilesQ = (td.dimQ + 31) / 32;
+  // the whole plane along an axis when it is short, else 64 (P) or 32 (Q)
+  td.TP = (int)(td.dimP <= 128 ? td.dimP : 64);
+  td.TQ = (int)(td.dimQ <= 64 ? td.dimQ : 32);
+  while ((long long)td.TP * td.TQ > kTileElems) td.TQ = (td.TQ + 1) / 2;
+  td.tilesP = (td.dimP + td.TP - 1) / td.TP;
+  td.tilesQ = (td.dimQ + td.TQ - 1) / td.TQ;
   long long batch = 1;
   for (int a = 0; a < td.nb; ++a) batch *= td.bdim[a];
   const long long blocks = batch * td.tilesP * td.tilesQ;
   CTM_REQUIRE(blocks < (1LL << 31), "permute: too many tiles");
-  hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx.stream, in,
+  const size_t lds = (size_t)td.TQ * (td.TP + 1) * sizeof(double);
+  hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)blocks), dim3(256), lds, ctx.stream, in,
                      out, td);
   CTM_HIP(hipGetLastError());
 }
