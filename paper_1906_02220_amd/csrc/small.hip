@@ -16,6 +16,9 @@ namespace ctm {
 namespace {
 
 constexpr int kRedBlocks = 512;  // fixed partition of the two-stage reductions
+// arrays up to this size are max-abs normalised by one workgroup (a chi = 96
+// corner has 9216 elements)
+constexpr int kNormaliseOneGroup = 16384;
 
 __device__ inline unsigned long long splitmix64(unsigned long long z) {
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -123,30 +126,52 @@ __global__ void maxabs_partial_kernel(const double* __restrict__ p, size_t n, do
   if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-__global__ void maxabs_final_kernel(const double* partial, int nb, double* log_slot, int* flag,
-                                    double* inv_out, double* inv_keep) {
+// 1 / m for the max-abs m of a normalised array (1 when m is 0 or not
+// finite: the array is left as it is and the flag raised).  One thread of the
+// launch records the flag, the log scale and the factor.
+__device__ inline double normalise_factor(double m, bool record, double* log_slot, int* flag,
+                                          double* inv_keep) {
+  const bool bad = !(m < INFINITY) || m == 0.0;
+  const double inv = bad ? 1.0 : 1.0 / m;
+  if (record) {
+    if (bad)
+      *flag = 1;
+    else
+      *log_slot += log(m);
+    if (inv_keep) *inv_keep = inv;
+  }
+  return inv;
+}
+
+// Second stage: every workgroup takes the maximum over the nb partial maxima
+// itself (the same value in each) and scales its share of p.
+__global__ void scale_by_max_kernel(double* p, size_t n, const double* __restrict__ partial,
+                                    int nb, double* log_slot, int* flag, double* inv_keep) {
   __shared__ double sh[256];
   double m = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, partial[i]);
   m = block_max256(m, sh);
-  if (threadIdx.x == 0) {
-    double inv = 1.0;
-    if (!(m < INFINITY) || m == 0.0) {
-      *flag = 1;
-    } else {
-      inv = 1.0 / m;
-      *log_slot += log(m);
-    }
-    *inv_out = inv;
-    if (inv_keep) *inv_keep = inv;
-  }
-}
-
-__global__ void scale_by_dev_kernel(double* p, size_t n, const double* s) {
-  const double f = *s;
+  const double f = normalise_factor(m, blockIdx.x == 0 && threadIdx.x == 0, log_slot, flag,
+                                    inv_keep);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
     p[i] *= f;
+}
+
+// An array of at most kNormaliseOneGroup elements (a corner) in one workgroup:
+// maximum, factor and scaling in one launch.  Each thread scales the elements
+// it read.
+__global__ void normalise_one_group_kernel(double* p, int n, double* log_slot, int* flag,
+                                           double* inv_keep) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = p[i];
+    m = isfinite(v) ? fmax(m, fabs(v)) : INFINITY;
+  }
+  m = block_max256(m, sh);
+  const double f = normalise_factor(m, threadIdx.x == 0, log_slot, flag, inv_keep);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] *= f;
 }
 
 __global__ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__ y,
@@ -935,13 +960,17 @@ void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
 
 void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag,
                       double* inv_keep) {
+  if (n <= (size_t)kNormaliseOneGroup) {
+    hipLaunchKernelGGL(normalise_one_group_kernel, dim3(1), dim3(256), 0, ctx.stream, p, (int)n,
+                       log_slot, flag, inv_keep);
+    CTM_HIP(hipGetLastError());
+    return;
+  }
   double* part = red_scratch(ctx);
-  double* inv = part + kRedBlocks;
   const int nb = grid_for(n, 256, kRedBlocks);
   hipLaunchKernelGGL(maxabs_partial_kernel, dim3(nb), dim3(256), 0, ctx.stream, p, n, part);
-  hipLaunchKernelGGL(maxabs_final_kernel, dim3(1), dim3(256), 0, ctx.stream, part, nb, log_slot,
-                     flag, inv, inv_keep);
-  hipLaunchKernelGGL(scale_by_dev_kernel, dim3(grid_for(n)), dim3(256), 0, ctx.stream, p, n, inv);
+  hipLaunchKernelGGL(scale_by_max_kernel, dim3(grid_for(n)), dim3(256), 0, ctx.stream, p, n, part,
+                     nb, log_slot, flag, inv_keep);
   CTM_HIP(hipGetLastError());
 }
 
