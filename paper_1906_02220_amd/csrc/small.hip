@@ -17,7 +17,7 @@ namespace {
 
 constexpr int kRedBlocks = 512;  // fixed partition of the two-stage reductions
 // arrays up to this size are max-abs normalised by one workgroup (a chi = 96
-// corner has 9216 elements)
+// corner has 9216 elements); 1024 threads x 16 elements
 constexpr int kNormaliseOneGroup = 16384;
 
 __device__ inline unsigned long long splitmix64(unsigned long long z) {
@@ -158,20 +158,39 @@ __global__ void scale_by_max_kernel(double* p, size_t n, const double* __restric
     p[i] *= f;
 }
 
-// An array of at most kNormaliseOneGroup elements (a corner) in one workgroup:
-// maximum, factor and scaling in one launch.  Each thread scales the elements
-// it read.
-__global__ void normalise_one_group_kernel(double* p, int n, double* log_slot, int* flag,
-                                           double* inv_keep) {
-  __shared__ double sh[256];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double v = p[i];
-    m = isfinite(v) ? fmax(m, fabs(v)) : INFINITY;
+// An array of at most kNormaliseOneGroup elements (a corner) in one workgroup
+// of 1024 threads: every thread loads its (at most 16) elements at once into
+// registers, the maximum goes through wave shuffles and LDS, and the scaled
+// values are written from the registers; one launch, one read.
+constexpr int kNormaliseThreads = 1024;
+constexpr int kNormalisePerThread = 16;
+static_assert(kNormaliseOneGroup <= kNormaliseThreads * kNormalisePerThread,
+              "one workgroup holds a whole small array in registers");
+__global__ __launch_bounds__(kNormaliseThreads) void normalise_one_group_kernel(
+    double* p, int n, double* log_slot, int* flag, double* inv_keep) {
+  __shared__ double wmax[kNormaliseThreads / 64];
+  const int t = threadIdx.x;
+  double v[kNormalisePerThread];
+#pragma unroll
+  for (int u = 0; u < kNormalisePerThread; ++u) {
+    const int i = t + u * kNormaliseThreads;
+    v[u] = i < n ? p[i] : 0.0;
   }
-  m = block_max256(m, sh);
-  const double f = normalise_factor(m, threadIdx.x == 0, log_slot, flag, inv_keep);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] *= f;
+  double m = 0.0;
+#pragma unroll
+  for (int u = 0; u < kNormalisePerThread; ++u) m = isfinite(v[u]) ? fmax(m, fabs(v[u])) : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((t & 63) == 0) wmax[t >> 6] = m;
+  __syncthreads();
+  m = 0.0;
+#pragma unroll
+  for (int w = 0; w < kNormaliseThreads / 64; ++w) m = fmax(m, wmax[w]);
+  const double f = normalise_factor(m, t == 0, log_slot, flag, inv_keep);
+#pragma unroll
+  for (int u = 0; u < kNormalisePerThread; ++u) {
+    const int i = t + u * kNormaliseThreads;
+    if (i < n) p[i] = v[u] * f;
+  }
 }
 
 __global__ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__ y,
@@ -961,8 +980,8 @@ void fill_normal(Context& ctx, double* Z, size_t count, unsigned long long seed,
 void normalise_maxabs(Context& ctx, double* p, size_t n, double* log_slot, int* flag,
                       double* inv_keep) {
   if (n <= (size_t)kNormaliseOneGroup) {
-    hipLaunchKernelGGL(normalise_one_group_kernel, dim3(1), dim3(256), 0, ctx.stream, p, (int)n,
-                       log_slot, flag, inv_keep);
+    hipLaunchKernelGGL(normalise_one_group_kernel, dim3(1), dim3(kNormaliseThreads), 0, ctx.stream,
+                       p, (int)n, log_slot, flag, inv_keep);
     CTM_HIP(hipGetLastError());
     return;
   }
