@@ -166,42 +166,93 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
   const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
   const int t = threadIdx.x;
   // 16-byte loads of two neighbours along the contiguous index (the caller
-  // passes a 16-byte aligned p and an even stride)
-  if (cs == 1) {
+  // passes a 16-byte aligned p and an even stride).  All eight loads of a
+  // thread are issued before any LDS write, so they are in flight together
+  // (a loop that wrote each value before the next load kept one in flight).
+  // A tile inside both bounds (all but the last along each axis) loads
+  // without branches; the bounds checks' joins would make the compiler wait
+  // for each load before the next.
+  constexpr int kLoads = 64 * 32 / 256;
+  double v0[kLoads], v1[kLoads];
+  const bool interior = r0 + 64 <= R && k0 + 64 <= K;
+  if (cs == 1 && interior) {
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int r = r0 + (idx >> 5), k = k0 + (idx & 31) * 2;
+      const d2v v = *(const d2v*)(p + r * rs + k);
+      v0[j] = v.x;
+      v1[j] = v.y;
+    }
+  } else if (interior) {
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int k = k0 + (idx >> 5), r = r0 + (idx & 31) * 2;
+      const d2v v = *(const d2v*)(p + r + k * cs);
+      v0[j] = v.x;
+      v1[j] = v.y;
+    }
+  } else if (cs == 1) {
     // rows contiguous along k: consecutive threads walk k
-    for (int idx = t; idx < 64 * 32; idx += 256) {
-      const int rr = idx >> 5, kk = (idx & 31) * 2;
-      const int r = r0 + rr, k = k0 + kk;
-      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int r = r0 + (idx >> 5), k = k0 + (idx & 31) * 2;
+      v0[j] = 0.0;
+      v1[j] = 0.0;
       if (r < R) {
         if (k + 1 < K) {
           const d2v v = *(const d2v*)(p + r * rs + k);
-          v0 = v.x;
-          v1 = v.y;
+          v0[j] = v.x;
+          v1[j] = v.y;
         } else if (k < K) {
-          v0 = p[r * rs + k];
+          v0[j] = p[r * rs + k];
         }
       }
-      tile[rr][kk] = v0;
-      tile[rr][kk + 1] = v1;
     }
   } else {
     // contiguous along r (rs == 1): consecutive threads walk r
-    for (int idx = t; idx < 64 * 32; idx += 256) {
-      const int kk = idx >> 5, rr = (idx & 31) * 2;
-      const int r = r0 + rr, k = k0 + kk;
-      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int k = k0 + (idx >> 5), r = r0 + (idx & 31) * 2;
+      v0[j] = 0.0;
+      v1[j] = 0.0;
       if (k < K) {
         if (r + 1 < R) {
           const d2v v = *(const d2v*)(p + r + k * cs);
-          v0 = v.x;
-          v1 = v.y;
+          v0[j] = v.x;
+          v1[j] = v.y;
         } else if (r < R) {
-          v0 = p[r + k * cs];
+          v0[j] = p[r + k * cs];
         }
       }
-      tile[rr][kk] = v0;
-      tile[rr + 1][kk] = v1;
+    }
+  }
+  // the scales of this thread's two rows (see below), fetched while the tile
+  // loads are in flight
+  double mrow[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = r0 + (t >> 3) + 32 * h;
+    mrow[h] = r < R ? mx[r] : 0.0;
+  }
+  if (cs == 1) {
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int rr = idx >> 5, kk = (idx & 31) * 2;
+      tile[rr][kk] = v0[j];
+      tile[rr][kk + 1] = v1[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const int idx = t + 256 * j;
+      const int kk = idx >> 5, rr = (idx & 31) * 2;
+      tile[rr][kk] = v0[j];
+      tile[rr + 1][kk] = v1[j];
     }
   }
   __syncthreads();
@@ -218,7 +269,7 @@ __global__ __launch_bounds__(256) void split_kernel(const double* __restrict__ p
     if (r >= R) break;
     const int kb = k0 + 8 * c8;
     if (kb >= Kp) continue;
-    const int e = scale_exponent(mx[r]);
+    const int e = scale_exponent(mrow[h]);
     __bf16 v[S][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
